@@ -1,0 +1,135 @@
+/*
+ * dsfft.h -- C ABI of the MI355X (gfx950) batched power-of-two FFT whose every
+ * radix-2 stage runs the dual-select six-FMA butterfly.
+ *
+ * Method: M. A. Bergach, "Dual-Select FMA Butterfly for FFT: Eliminating Twiddle
+ * Factor Singularities with Bounded Precomputed Ratios", arXiv 2604.00567.
+ *
+ * Transform (Sec. I, eq. (1)): forward and unnormalised,
+ *     X[k] = sum_{n<N} x[n] W^{nk},   W = exp(-j 2 pi / N),
+ * computed as log2(N) radix-2 Stockham DIT passes; pass s (span L = 2^s) pairs
+ * a = Y[r][j] with b = Y[r + N/L][j] and forms A = a + W^{jN/L} b, B = a - W^{jN/L} b
+ * with exactly six FMAs (eqs. (berg-s)-(berg-B) on the cosine path,
+ * eqs. (lf-s)-(lf-B) on the sine path, each FMA rounded once in the working
+ * precision).  The twiddle table decides the path per twiddle (Algorithm 1).
+ *
+ * Data layout: interleaved complex, transform-contiguous.  Element n of
+ * transform b sits at index b*N + n; an element is (re, im) as two binary16
+ * values (FFT_F16, 4 bytes) or two binary32 values (FFT_F32, 8 bytes).
+ * Input and output use the same layout, output in natural frequency order.
+ *
+ * Pointers named in/out are device pointers (HBM), owned by the caller and
+ * aligned to the element size.  in == out (in place) is allowed; partial overlap is not.
+ * Streams are hipStream_t values passed as void* (NULL = the null stream).
+ *
+ * Errors: functions returning int give FFT_OK (0) or a negative code; those
+ * returning a pointer give NULL on error.  fft_last_error() returns a
+ * thread-local message for the last error on the calling thread.  No call
+ * aborts the process on a user error.
+ */
+#ifndef DSFFT_H
+#define DSFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { FFT_OK = 0, FFT_EINVAL = -1, FFT_ENOMEM = -2, FFT_EHIP = -3, FFT_EUNSUPPORTED = -4 };
+
+/* Storage and arithmetic precision of data and table. */
+typedef enum { FFT_F16 = 0, FFT_F32 = 1 } fft_dtype;
+
+/*
+ * Twiddle-table kind (Sec. II-III):
+ *   FFT_TABLE_DUAL_SELECT  Algorithm 1: per twiddle, cosine factorisation
+ *                          (mult cos, ratio tan) when |cos| >= |sin|, else the
+ *                          sine one (mult sin, ratio cot); |ratio| <= 1 (Theorem).
+ *   FFT_TABLE_LINZER_FEIG  sine factorisation everywhere, sin clamped to +1e-7
+ *                          where |sin| < 1e-7 (the clamp named in Sec. I).
+ *   FFT_TABLE_COSINE       cosine factorisation everywhere (Sec. II-C).
+ *   FFT_TABLE_LF_W0_EXEMPT Linzer-Feig with the W^0 entry taken on the cosine
+ *                          path (no clamp needed); a finite comparison table.
+ */
+typedef enum {
+    FFT_TABLE_DUAL_SELECT = 0,
+    FFT_TABLE_LINZER_FEIG = 1,
+    FFT_TABLE_COSINE = 2,
+    FFT_TABLE_LF_W0_EXEMPT = 3
+} fft_table_kind;
+
+typedef struct fft_plan fft_plan;     /* opaque; immutable after creation   */
+
+/* Message for the last error on this thread ("" if none).  Never NULL. */
+const char* fft_last_error(void);
+
+/*
+ * Builds a plan for `batch` transforms of size n (power of two, 2 <= n <= 2^20,
+ * batch >= 1).  Generates the table of `kind` in FP64 on the host (Algorithm 1:
+ * theta = -(2 pi k)/N, cos/sin, the |cos| >= |sin| select, the ratio division),
+ * rounds mult and ratio once to `dtype`, and uploads it to HBM (shared across
+ * plans of the same dtype and kind).  Chooses the kernel configuration (tuned
+ * record if one exists, else a fixed rule) and, for n beyond one workgroup's
+ * LDS, a two-pass schedule with a plan-owned workspace.
+ * Returns NULL on error (FFT_EINVAL for bad arguments, FFT_ENOMEM, FFT_EHIP).
+ */
+fft_plan* fft_plan_create(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind);
+
+/*
+ * Enqueues the batched forward FFT out = FFT(in) on `stream` and returns
+ * without synchronising.  in/out: device pointers of batch*n elements each.
+ * A plan must not run concurrently on two streams (its workspace is shared).
+ * Returns FFT_OK, FFT_EINVAL (null plan/pointer, misalignment, partial overlap)
+ * or FFT_EHIP (launch failure; message in fft_last_error()).
+ */
+int fft_execute(fft_plan* plan, const void* in, void* out, void* stream);
+
+/* Waits for the plan's last execution, then frees it.  NULL-safe. */
+void fft_destroy(fft_plan* plan);
+
+/*
+ * Host-only (no GPU needed): the table of `kind` for size n rounded to `dtype`,
+ * k in [0, n/2).  mult_out/ratio_out receive n/2 values of the dtype's storage
+ * type (uint16 binary16 bits or float), path_out n/2 bytes (0 cosine, 1 sine).
+ * Any output pointer may be NULL.  Returns FFT_OK or FFT_EINVAL.
+ */
+int fft_table_build(int64_t n, fft_dtype dtype, fft_table_kind kind,
+                    void* mult_out, void* ratio_out, uint8_t* path_out);
+
+/* The plan's parameters and its kernel choice, for tests and reports.
+ * config_out receives a NUL-terminated description (up to `cap` bytes). */
+int fft_plan_info(const fft_plan* plan, int64_t* n, int64_t* batch, int* dtype, int* kind,
+                  char* config_out, size_t cap);
+
+/* Bytes of device workspace the plan uses (0 for single-pass sizes). */
+int fft_plan_workspace_bytes(const fft_plan* plan, size_t* bytes);
+
+/*
+ * Replaces the plan-owned workspace by caller memory (device pointer of at
+ * least fft_plan_workspace_bytes bytes, 16-byte aligned), e.g. from torch's
+ * allocator.  The caller keeps it alive while the plan may run.
+ */
+int fft_plan_set_workspace(fft_plan* plan, void* dev_ptr, size_t bytes);
+
+/*
+ * Same as fft_plan_create but with an explicit kernel choice, for the tuner and
+ * for tests that compare configurations: variant_a / variant_b index the
+ * compiled configurations for the size (single kernel, or the column / row
+ * kernels of the two-pass schedule); two_pass = 1 forces the two-pass schedule
+ * where a single kernel would fit.  Returns NULL (FFT_EUNSUPPORTED) when no
+ * such configuration exists.
+ */
+fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                                  int variant_a, int variant_b, int two_pass);
+
+/* Number of compiled configurations for (n, dtype): *single for the
+ * one-kernel schedule, *cols and *rows for the two kernels of the two-pass one. */
+int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSFFT_H */

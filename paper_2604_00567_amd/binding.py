@@ -1,0 +1,200 @@
+"""ctypes binding of libdsfft.so: the C ABI of include/dsfft.h, same names.
+
+Argument marshalling only: every FFT step runs in the HIP kernels of the
+library.  Importing this module loads the library and raises if it has not
+been built (there is no other path).  Torch is used only to hand device
+pointers and streams through (``Plan.execute`` accepts torch tensors).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdsfft.so")
+HEADER = os.path.join(os.path.dirname(_HERE), "include", "dsfft.h")
+
+FFT_OK, FFT_EINVAL, FFT_ENOMEM, FFT_EHIP, FFT_EUNSUPPORTED = 0, -1, -2, -3, -4
+FFT_F16, FFT_F32 = 0, 1
+DTYPES = {"f16": FFT_F16, "f32": FFT_F32}
+KINDS = {"dual_select": 0, "linzer_feig": 1, "cosine": 2, "lf_w0_exempt": 3}
+ELEM_BYTES = {FFT_F16: 4, FFT_F32: 8}
+
+
+class FFTError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"dsfft error {code}: {msg}")
+        self.code = code
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2604_00567_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_vp, _i64, _int, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+_SIGS = {
+    "fft_last_error": ([], ctypes.c_char_p),
+    "fft_plan_create": ([_i64, _i64, _int, _int], _vp),
+    "fft_plan_create_variant": ([_i64, _i64, _int, _int, _int, _int, _int], _vp),
+    "fft_execute": ([_vp, _vp, _vp, _vp], _int),
+    "fft_destroy": ([_vp], None),
+    "fft_table_build": ([_i64, _int, _int, _vp, _vp, _vp], _int),
+    "fft_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int),
+                       ctypes.POINTER(_int), ctypes.c_char_p, _sz], _int),
+    "fft_plan_workspace_bytes": ([_vp, ctypes.POINTER(_sz)], _int),
+    "fft_plan_set_workspace": ([_vp, _vp, _sz], _int),
+    "fft_config_count": ([_i64, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                          ctypes.POINTER(_int)], _int),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+
+def declared_functions() -> list[str]:
+    """Function names declared in include/dsfft.h."""
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_0-9]+)\s*\(", text)))
+
+
+def _dt(dtype) -> int:
+    return DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+
+
+def _kd(kind) -> int:
+    return KINDS[kind] if isinstance(kind, str) else int(kind)
+
+
+def fft_last_error() -> str:
+    return _lib.fft_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != FFT_OK:
+        raise FFTError(rc, fft_last_error())
+
+
+def fft_plan_create(n: int, batch: int, dtype, kind) -> int:
+    h = _lib.fft_plan_create(n, batch, _dt(dtype), _kd(kind))
+    if not h:
+        raise FFTError(FFT_EINVAL, fft_last_error())
+    return h
+
+
+def fft_plan_create_variant(n: int, batch: int, dtype, kind, variant_a: int = 0,
+                            variant_b: int = 0, two_pass: bool = False) -> int:
+    h = _lib.fft_plan_create_variant(n, batch, _dt(dtype), _kd(kind), variant_a, variant_b,
+                                     1 if two_pass else 0)
+    if not h:
+        raise FFTError(FFT_EUNSUPPORTED, fft_last_error())
+    return h
+
+
+def fft_execute(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _check(_lib.fft_execute(plan, in_ptr, out_ptr, stream))
+
+
+def fft_destroy(plan: int) -> None:
+    _lib.fft_destroy(plan)
+
+
+def fft_table_build(n: int, dtype, kind):
+    """(mult, ratio, path) of the size-n table rounded to dtype (host only)."""
+    dt = _dt(dtype)
+    h = n // 2
+    st = np.uint16 if dt == FFT_F16 else np.float32
+    mult = np.empty(h, st)
+    ratio = np.empty(h, st)
+    path = np.empty(h, np.uint8)
+    _check(_lib.fft_table_build(n, dt, _kd(kind), mult.ctypes.data, ratio.ctypes.data,
+                                path.ctypes.data))
+    if dt == FFT_F16:
+        mult, ratio = mult.view(np.float16), ratio.view(np.float16)
+    return mult, ratio, path
+
+
+def fft_plan_info(plan: int) -> dict:
+    n, b = _i64(), _i64()
+    d, k = _int(), _int()
+    buf = ctypes.create_string_buffer(512)
+    _check(_lib.fft_plan_info(plan, ctypes.byref(n), ctypes.byref(b), ctypes.byref(d),
+                              ctypes.byref(k), buf, 512))
+    return {"n": n.value, "batch": b.value, "dtype": d.value, "kind": k.value,
+            "config": buf.value.decode()}
+
+
+def fft_plan_workspace_bytes(plan: int) -> int:
+    s = _sz()
+    _check(_lib.fft_plan_workspace_bytes(plan, ctypes.byref(s)))
+    return s.value
+
+
+def fft_plan_set_workspace(plan: int, dev_ptr: int, nbytes: int) -> None:
+    _check(_lib.fft_plan_set_workspace(plan, dev_ptr, nbytes))
+
+
+def fft_config_count(n: int, dtype) -> tuple[int, int, int]:
+    a, b, c = _int(), _int(), _int()
+    _check(_lib.fft_config_count(n, _dt(dtype), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+# ----------------------------------------------------------- torch marshalling
+
+def _torch_stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _check_tensor(t, n: int, batch: int, dt: int):
+    import torch
+    want = torch.float16 if dt == FFT_F16 else torch.float32
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    ok_dtype = t.dtype == want or (dt == FFT_F32 and t.dtype == torch.complex64) or \
+        (dt == FFT_F16 and t.dtype == torch.complex32)
+    if not ok_dtype:
+        raise ValueError(f"tensor dtype {t.dtype} does not match the plan")
+    if t.numel() * t.element_size() != n * batch * ELEM_BYTES[dt]:
+        raise ValueError("tensor size does not match n * batch complex elements")
+
+
+class Plan:
+    """Owns a plan handle; execute() takes torch tensors laid out (batch, n, 2)."""
+
+    def __init__(self, n: int, batch: int, dtype="f16", kind="dual_select", variant=None):
+        self.n, self.batch, self.dtype, self.kind = n, batch, _dt(dtype), _kd(kind)
+        if variant is None:
+            self.handle = fft_plan_create(n, batch, self.dtype, self.kind)
+        else:
+            self.handle = fft_plan_create_variant(n, batch, self.dtype, self.kind, *variant)
+
+    def execute(self, x, y, stream=None) -> None:
+        _check_tensor(x, self.n, self.batch, self.dtype)
+        _check_tensor(y, self.n, self.batch, self.dtype)
+        fft_execute(self.handle, x.data_ptr(), y.data_ptr(), _torch_stream(stream))
+
+    def info(self) -> dict:
+        return fft_plan_info(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            fft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,338 @@
+// C ABI of the dual-select FFT library (declared in include/dsfft.h): plans,
+// table cache, schedule choice and launches.
+#include "dsfft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "fft_device.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+#include "tables.hpp"
+
+namespace dsfft {
+
+static thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_error(hipError_t e, const char* where) {
+    return set_error(FFT_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+// ------------------------------------------------------------- table cache
+
+DeviceTable::~DeviceTable() {
+    if (ptr) (void)hipFree(ptr);
+}
+
+static std::mutex g_table_mu;
+static std::map<std::tuple<int, int, int>, std::shared_ptr<DeviceTable>> g_tables;
+
+// Level-ordered table with capacity >= n for (device, dtype, kind), shared by
+// every plan that needs it.  A larger request replaces the cached table; plans
+// holding the old one keep it alive.
+int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lock(g_table_mu);
+    auto key = std::make_tuple(dev, dtype, kind);
+    auto it = g_tables.find(key);
+    if (it != g_tables.end() && it->second->ncap >= n) {
+        *out = it->second;
+        return FFT_OK;
+    }
+    const int64_t ncap = std::max<int64_t>(n, 4096);
+    std::vector<uint8_t> img = build_level_table(ncap, dtype, kind);
+    auto t = std::make_shared<DeviceTable>();
+    t->ncap = ncap;
+    t->bytes = img.size();
+    e = hipMalloc(&t->ptr, img.size());
+    if (e != hipSuccess) {
+        t->ptr = nullptr;
+        return e == hipErrorOutOfMemory ? set_error(FFT_ENOMEM, "table allocation failed")
+                                        : hip_error(e, "hipMalloc(table)");
+    }
+    e = hipMemcpy(t->ptr, img.data(), img.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, "hipMemcpy(table)");
+    g_tables[key] = t;
+    *out = t;
+    return FFT_OK;
+}
+
+// ------------------------------------------------------------ kernel choice
+
+static const KernelCfg* table_for(int dtype, int* count) {
+    return dtype == DT_F16 ? kernel_table_f16(count) : kernel_table_f32(count);
+}
+
+const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant) {
+    int cnt = 0;
+    const KernelCfg* t = table_for(dtype, &cnt);
+    int seen = 0;
+    for (int i = 0; i < cnt; ++i) {
+        if (t[i].mode != mode || t[i].log_nu != log_nu) continue;
+        if (t[i].lds_bytes > 160 * 1024) continue;
+        if (seen++ == variant) return &t[i];
+    }
+    return nullptr;
+}
+
+int count_kernels(int dtype, int mode, int log_nu) {
+    int n = 0;
+    while (find_kernel(dtype, mode, log_nu, n)) ++n;
+    return n;
+}
+
+std::string describe(const KernelCfg* k) {
+    if (!k) return "none";
+    static const char* modes[] = {"small", "cols", "rows"};
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],t=%d,lds=%zu",
+                  modes[k->mode], k->log_nu, k->log_e, k->upw, k->lr[0], k->lr[1], k->lr[2],
+                  k->threads, k->lds_bytes);
+    return buf;
+}
+
+// Largest single-kernel size per dtype, and the two-pass split.
+static int small_limit(int dtype) { return dtype == DT_F16 ? 14 : 14; }
+
+int choose_schedule(fft_plan* p, const int* variants) {
+    const int m = p->log_n;
+    const int v0 = variants ? variants[0] : 0, v1 = variants ? variants[1] : 0;
+    if (m <= small_limit(p->dtype) && (!variants || variants[2] == 0)) {
+        p->k1 = find_kernel(p->dtype, MODE_SMALL, m, v0);
+        p->k2 = nullptr;
+        if (!p->k1) return set_error(FFT_EUNSUPPORTED, "no kernel for this size");
+        return FFT_OK;
+    }
+    const int m1 = (m + 1) / 2, m2 = m - m1;     // columns of 2^m1, rows of 2^m2
+    p->k1 = find_kernel(p->dtype, MODE_COLS, m1, v0);
+    p->k2 = find_kernel(p->dtype, MODE_ROWS, m2, v1);
+    if (!p->k1 || !p->k2) return set_error(FFT_EUNSUPPORTED, "no two-pass kernels for this size");
+    return FFT_OK;
+}
+
+int elem_bytes(int dtype) { return dtype == DT_F16 ? 4 : 8; }
+
+// Workspace: two-pass schedules stage the intermediate per chunk of
+// transforms; a chunk is capped at 64 MiB so the intermediate can stay in the
+// memory-side cache between the two kernels.
+void size_workspace(fft_plan* p) {
+    if (!p->k2) {
+        p->chunk = p->batch;
+        p->ws_need = 0;
+        return;
+    }
+    const size_t per = (size_t)p->n * elem_bytes(p->dtype);
+    const size_t cap = (size_t)64 << 20;
+    int64_t chunk = (int64_t)std::max<size_t>(1, cap / per);
+    chunk = std::min<int64_t>(chunk, p->batch);
+    p->chunk = chunk;
+    p->ws_need = (size_t)chunk * per;
+}
+
+int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
+    const void* lt = p->table->ptr;
+    if (!p->k2) {
+        hipError_t e = p->k1->launch(in, out, lt, p->batch, 0, s);
+        if (e != hipSuccess) return hip_error(e, "launch");
+        return FFT_OK;
+    }
+    const int m1 = p->k1->log_nu, m2 = p->k2->log_nu;
+    const size_t eb = (size_t)elem_bytes(p->dtype);
+    for (int64_t b0 = 0; b0 < p->batch; b0 += p->chunk) {
+        const int64_t nb = std::min<int64_t>(p->chunk, p->batch - b0);
+        const char* src = (const char*)in + (size_t)b0 * p->n * eb;
+        char* dst = (char*)out + (size_t)b0 * p->n * eb;
+        hipError_t e = p->k1->launch(src, p->ws, lt, nb << m2, m2, s);
+        if (e != hipSuccess) return hip_error(e, "launch(cols)");
+        e = p->k2->launch(p->ws, dst, lt, nb << m1, m1, s);
+        if (e != hipSuccess) return hip_error(e, "launch(rows)");
+    }
+    return FFT_OK;
+}
+
+static bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
+
+fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants) {
+    if (!is_pow2(n) || n > (int64_t(1) << 20)) {
+        set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
+        return nullptr;
+    }
+    if (batch < 1) {
+        set_error(FFT_EINVAL, "batch must be >= 1");
+        return nullptr;
+    }
+    if (dtype != DT_F16 && dtype != DT_F32) {
+        set_error(FFT_EINVAL, "dtype must be FFT_F16 or FFT_F32");
+        return nullptr;
+    }
+    if (kind < 0 || kind > 3) {
+        set_error(FFT_EINVAL, "unknown table kind");
+        return nullptr;
+    }
+    std::unique_ptr<fft_plan> p(new fft_plan());
+    p->n = n;
+    p->batch = batch;
+    p->dtype = dtype;
+    p->kind = kind;
+    p->log_n = 0;
+    while ((int64_t(1) << p->log_n) < n) ++p->log_n;
+    hipError_t e = hipGetDevice(&p->device);
+    if (e != hipSuccess) {
+        hip_error(e, "hipGetDevice");
+        return nullptr;
+    }
+    if (get_table(n, dtype, kind, &p->table) != FFT_OK) return nullptr;
+    if (choose_schedule(p.get(), variants) != FFT_OK) return nullptr;
+    size_workspace(p.get());
+    if (p->ws_need) {
+        e = hipMalloc(&p->ws, p->ws_need);
+        if (e != hipSuccess) {
+            p->ws = nullptr;
+            set_error(e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP, "workspace allocation failed");
+            return nullptr;
+        }
+        p->ws_owned = true;
+        p->ws_bytes = p->ws_need;
+    }
+    e = hipEventCreateWithFlags(&p->last, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        hip_error(e, "hipEventCreate");
+        return nullptr;
+    }
+    return p.release();
+}
+
+static bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    if (x == y) return false;
+    return x < y + bytes && y < x + bytes;
+}
+
+int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s) {
+    if (!p) return set_error(FFT_EINVAL, "null plan");
+    if (!in || !out) return set_error(FFT_EINVAL, "null data pointer");
+    const size_t eb = (size_t)elem_bytes(p->dtype);
+    if (((uintptr_t)in % eb) || ((uintptr_t)out % eb))
+        return set_error(FFT_EINVAL, "data pointers must be aligned to the element size");
+    if (ranges_partially_overlap(in, out, (size_t)p->n * p->batch * eb))
+        return set_error(FFT_EINVAL, "in and out partially overlap");
+    int rc = launch_plan(p, in, out, s);
+    if (rc != FFT_OK) return rc;
+    hipError_t e = hipEventRecord(p->last, s);
+    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    return FFT_OK;
+}
+
+}  // namespace dsfft
+
+fft_plan::~fft_plan() {
+    if (last) {
+        (void)hipEventSynchronize(last);
+        (void)hipEventDestroy(last);
+    }
+    if (ws && ws_owned) (void)hipFree(ws);
+}
+
+using namespace dsfft;
+
+extern "C" {
+
+const char* fft_last_error(void) { return g_last_error.c_str(); }
+
+fft_plan* fft_plan_create(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind) {
+    return plan_create(n, batch, (int)dtype, (int)kind, nullptr);
+}
+
+int fft_execute(fft_plan* plan, const void* in, void* out, void* stream) {
+    return plan_execute(plan, in, out, (hipStream_t)stream);
+}
+
+void fft_destroy(fft_plan* plan) { delete plan; }
+
+int fft_table_build(int64_t n, fft_dtype dtype, fft_table_kind kind, void* mult_out,
+                    void* ratio_out, uint8_t* path_out) {
+    if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
+        return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32) return set_error(FFT_EINVAL, "bad dtype");
+    if ((int)kind < 0 || (int)kind > 3) return set_error(FFT_EINVAL, "bad table kind");
+    build_flat_table(n, (int)dtype, (int)kind, mult_out, ratio_out, path_out);
+    return FFT_OK;
+}
+
+int fft_plan_info(const fft_plan* p, int64_t* n, int64_t* batch, int* dtype, int* kind,
+                  char* config_out, size_t cap) {
+    if (!p) return set_error(FFT_EINVAL, "null plan");
+    if (n) *n = p->n;
+    if (batch) *batch = p->batch;
+    if (dtype) *dtype = p->dtype;
+    if (kind) *kind = p->kind;
+    if (config_out && cap) {
+        std::string d = describe(p->k1);
+        if (p->k2) d += " | " + describe(p->k2) + " | chunk=" + std::to_string(p->chunk);
+        std::snprintf(config_out, cap, "%s", d.c_str());
+    }
+    return FFT_OK;
+}
+
+int fft_plan_workspace_bytes(const fft_plan* p, size_t* bytes) {
+    if (!p || !bytes) return set_error(FFT_EINVAL, "null argument");
+    *bytes = p->ws_need;
+    return FFT_OK;
+}
+
+int fft_plan_set_workspace(fft_plan* p, void* dev_ptr, size_t bytes) {
+    if (!p) return set_error(FFT_EINVAL, "null plan");
+    if (p->ws_need == 0) return FFT_OK;
+    if (!dev_ptr || bytes < p->ws_need || ((uintptr_t)dev_ptr % 16))
+        return set_error(FFT_EINVAL, "workspace too small, null or misaligned");
+    if (p->last) (void)hipEventSynchronize(p->last);
+    if (p->ws && p->ws_owned) (void)hipFree(p->ws);
+    p->ws = dev_ptr;
+    p->ws_bytes = bytes;
+    p->ws_owned = false;
+    return FFT_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                                  int variant_a, int variant_b, int two_pass) {
+    if (variant_a < 0 || variant_b < 0) {
+        set_error(FFT_EINVAL, "negative variant");
+        return nullptr;
+    }
+    const int v[3] = {variant_a, variant_b, two_pass ? 1 : 0};
+    return plan_create(n, batch, (int)dtype, (int)kind, v);
+}
+
+int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows) {
+    if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
+        return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
+    int m = 0;
+    while ((int64_t(1) << m) < n) ++m;
+    const int m1 = (m + 1) / 2, m2 = m - m1;
+    if (single) *single = count_kernels((int)dtype, MODE_SMALL, m);
+    if (cols) *cols = count_kernels((int)dtype, MODE_COLS, m1);
+    if (rows) *rows = count_kernels((int)dtype, MODE_ROWS, m2);
+    return FFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,314 @@
+// Device side of the dual-select FFT for gfx950 (CDNA4, wave64).
+//
+// One kernel template covers three ways of cutting a batch of transforms into
+// "units", each unit being a run of consecutive radix-2 Stockham stages done
+// inside one workgroup:
+//   MODE_SMALL  the whole transform is one unit (N fits one workgroup's LDS);
+//   MODE_COLS   first kernel of the two-pass schedule: stages 1..log2(NU) of
+//               the decimated column x[r0 + (N/NU) i], i < NU, per unit;
+//   MODE_ROWS   second kernel: stages log2(N/NU)+1..log2(N) of row q0 of the
+//               intermediate Y[i][q0], i < NU, per unit.
+// Inside a unit, stages are fused into register passes of radix R = 2^LR; each
+// lane holds E elements (E/R groups of R) and runs the pass's LR radix-2 stages
+// in registers; passes exchange data through LDS.
+//
+// Every radix-2 butterfly is the six-FMA butterfly of the paper (arXiv
+// 2604.00567): eqs. (berg-s)-(berg-B) on the cosine path, eqs. (lf-s)-(lf-B)
+// on the sine path, with the same operands, twiddle and FMA association as the
+// radix-2 Stockham definition, so fusing stages changes no rounding.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsfft {
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+
+// Device twiddle entry, binary16 plan.  w = (sigma*m, m) as two halves (low =
+// sigma*m), sigma = +1 on the cosine path and -1 on the sine path; ts carries
+// the path as a rotate amount in its low 16 bits (0 cosine, 16 sine) and the
+// ratio t as a binary16 value in its high 16 bits.
+struct TwH {
+    uint32_t w;
+    uint32_t ts;
+};
+
+// Device twiddle entry, binary32 plan: (sigma*m, m, t) and a lane mask that is
+// all ones on the sine path.
+struct __attribute__((aligned(16))) TwF {
+    float sm;
+    float m;
+    float t;
+    uint32_t mask;
+};
+
+__device__ __forceinline__ h2_t as_h2(uint32_t u) { return __builtin_bit_cast(h2_t, u); }
+__device__ __forceinline__ uint32_t as_u32(h2_t h) { return __builtin_bit_cast(uint32_t, h); }
+
+// Six-FMA butterfly, binary16 (three packed v_pk_fma_f16 = six FMAs).
+//   c = b on the cosine path, (b_i, b_r) on the sine path (one v_alignbit);
+//   (s1, s2) = (c.lo - t c.hi, t c.lo + c.hi)
+//     cosine: (b_r - t b_i, t b_r + b_i)             eq. (berg-s)
+//     sine:   (b_i - t b_r, t b_i + b_r)             eq. (lf-s), s2 read as b_r + t b_i
+//   A = a + (s1, s2) * (sigma m, m),  B = a - (s1, s2) * (sigma m, m)
+//     cosine: A_r = a_r + s1 m, A_i = a_i + s2 m     eqs. (berg-A), (berg-B)
+//     sine:   A_r = a_r - s1 m, A_i = a_i + s2 m     eqs. (lf-A), (lf-B)
+// Negating an operand is exact, so each lane computes the same FMAs as the
+// printed equations.
+__device__ __forceinline__ void bfly(uint32_t& a, uint32_t& b, const TwH tw) {
+    const uint32_t c = __builtin_amdgcn_alignbit(b, b, tw.ts);
+    const h2_t cv = as_h2(c);
+    const h2_t tv = as_h2(tw.ts);
+    const h2_t w = as_h2(tw.w);
+    const h2_t av = as_h2(a);
+    h2_t tt;
+    tt.x = -tv.y;
+    tt.y = tv.y;
+    const h2_t s = __builtin_elementwise_fma(tt, cv.yx, cv);
+    const h2_t A = __builtin_elementwise_fma(s, w, av);
+    const h2_t B = __builtin_elementwise_fma(-s, w, av);
+    a = as_u32(A);
+    b = as_u32(B);
+}
+
+// Six-FMA butterfly, binary32 (six v_fma_f32); the path picks (c_r, c_i) from
+// (b_r, b_i) or (b_i, b_r) with a bitwise select on the table's lane mask.
+__device__ __forceinline__ void bfly(f2_t& a, f2_t& b, const TwF tw) {
+    const uint32_t br = __builtin_bit_cast(uint32_t, b.x);
+    const uint32_t bi = __builtin_bit_cast(uint32_t, b.y);
+    const float cr = __builtin_bit_cast(float, (tw.mask & bi) | (~tw.mask & br));
+    const float ci = __builtin_bit_cast(float, (tw.mask & br) | (~tw.mask & bi));
+    const float s1 = __builtin_fmaf(-tw.t, ci, cr);
+    const float s2 = __builtin_fmaf(tw.t, cr, ci);
+    f2_t A, B;
+    A.x = __builtin_fmaf(s1, tw.sm, a.x);
+    A.y = __builtin_fmaf(s2, tw.m, a.y);
+    B.x = __builtin_fmaf(-s1, tw.sm, a.x);
+    B.y = __builtin_fmaf(-s2, tw.m, a.y);
+    a = A;
+    b = B;
+}
+
+template <class E> struct TwOf;
+template <> struct TwOf<uint32_t> { using type = TwH; };
+template <> struct TwOf<f2_t> { using type = TwF; };
+
+// Level-ordered twiddle table: entry L/2 + j is T_L[j] = W_L^j for span L (a
+// power of two) and j < L/2, stored as TwH/TwF.  Since theta = -(2 pi j)/L
+// scales exactly by powers of two, T_L[j] equals T_N[j N / L] bit for bit, so
+// one table of capacity N_cap serves every N <= N_cap.  For a group whose
+// butterflies have global column index j = qg + Lg0 * (2^(t-1) + e) in stage t
+// of a radix-R pass, the twiddle is entry qg + Lg0 * c with c = 2^(t-1) + e in
+// [1, R).
+
+// Radix-R register pass on one group of R = 2^LR elements (v[0..R)).  Stage t
+// (1..LR) pairs v[i + 2He] with v[i + H + 2He] (H = R >> t, i < H, e < 2^(t-1))
+// under twiddle c = 2^(t-1) + e, and writes A to v[i + He], B to v[i + He + R/2].
+// On entry v[i] = Y[r + M i][q]; on exit v[e] = Y'[r][q + L0 e].
+template <int LR, class E, class TW>
+__device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
+    constexpr int R = 1 << LR;
+#pragma unroll
+    for (int t = 1; t <= LR; ++t) {
+        const int H = R >> t;
+        E nv[R];
+#pragma unroll
+        for (int e = 0; e < (1 << (t - 1)); ++e) {
+#pragma unroll
+            for (int i = 0; i < H; ++i) {
+                E a = v[i + 2 * H * e];
+                E b = v[i + H + 2 * H * e];
+                bfly(a, b, tw[(1 << (t - 1)) + e]);
+                nv[i + H * e] = a;
+                nv[i + H * e + R / 2] = b;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; ++k) v[k] = nv[k];
+    }
+}
+
+enum { MODE_SMALL = 0, MODE_COLS = 1, MODE_ROWS = 2 };
+
+// ------------------------------------------------------------ compile-time plan
+
+template <int LOG_NU, int LR0, int LR1, int LR2>
+struct PassPlan {
+    static constexpr int NP = LR1 == 0 ? 1 : (LR2 == 0 ? 2 : 3);
+    static constexpr int lr(int p) { return p == 0 ? LR0 : (p == 1 ? LR1 : LR2); }
+    // log2 of the span before pass p
+    static constexpr int log_l0(int p) { return p == 0 ? 0 : (p == 1 ? LR0 : LR0 + LR1); }
+    // log2 of M after pass p: residues left = NU / (R_p L0_p)
+    static constexpr int log_m(int p) { return LOG_NU - log_l0(p) - lr(p); }
+    // LDS padding for the exchange after pass p: PAD elements per row of M_p
+    // elements, PAD = M_{p+1} (residues left after the next pass) when that is
+    // below 32, which spreads group-fast reads of consecutive columns over banks.
+    static constexpr int pad(int p) {
+        return (p + 1 < NP && log_m(p + 1) < 5) ? (1 << log_m(p + 1)) : 0;
+    }
+    static constexpr int padded(int p) {
+        return (1 << LOG_NU) + ((1 << LOG_NU) >> log_m(p)) * pad(p);
+    }
+    static constexpr int region() {
+        int r = 1 << LOG_NU;
+        for (int p = 0; p + 1 < NP; ++p) r = padded(p) > r ? padded(p) : r;
+        return r | 1;   // odd stride between units
+    }
+};
+
+// ------------------------------------------------------------------ the kernel
+
+// Geometry of one unit inside its transform.
+struct UnitGeom {
+    int64_t base_in, base_out, in_stride, out_stride;
+    int q0, log_lb;
+};
+
+template <int LOG_NU, int MODE>
+__device__ __forceinline__ UnitGeom unit_geom(int64_t unit, int log_m) {
+    UnitGeom u;
+    u.in_stride = u.out_stride = 1;
+    u.q0 = 0;
+    u.log_lb = 0;
+    if (MODE == MODE_SMALL) {
+        u.base_in = u.base_out = unit << LOG_NU;
+    } else if (MODE == MODE_COLS) {
+        const int64_t b = unit >> log_m;
+        const int64_t r0 = unit & ((int64_t(1) << log_m) - 1);
+        u.base_in = u.base_out = (b << (log_m + LOG_NU)) + r0;
+        u.in_stride = u.out_stride = int64_t(1) << log_m;
+    } else {
+        const int64_t b = unit >> log_m;
+        u.q0 = (int)(unit & ((int64_t(1) << log_m) - 1));
+        u.log_lb = log_m;
+        u.base_in = (b << (log_m + LOG_NU)) + ((int64_t)u.q0 << LOG_NU);
+        u.base_out = (b << (log_m + LOG_NU)) + u.q0;
+        u.out_stride = int64_t(1) << log_m;
+    }
+    return u;
+}
+
+// One register pass P of the unit schedule: gather (global or LDS), twiddles,
+// LR radix-2 stages per group, scatter (LDS or global).
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int P>
+__device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
+                                          const E* in, E* out, int64_t ublk, int64_t units,
+                                          int log_m) {
+    using TW = typename TwOf<E>::type;
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2>;
+    constexpr int NP = PP::NP;
+    if constexpr (P < NP) {
+        constexpr int NU = 1 << LOG_NU;
+        constexpr int EL = 1 << LOG_E;
+        constexpr int G = NU / EL;
+        constexpr int RS = PP::region();
+        constexpr int LR = PP::lr(P);
+        constexpr int R = 1 << LR;
+        constexpr int L0 = 1 << PP::log_l0(P);
+        constexpr int LOGM = PP::log_m(P);
+        constexpr int M = 1 << LOGM;
+        constexpr int GPL = EL / R;
+        constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
+        const int tid = threadIdx.x;
+        const int ul = unit_fast ? (tid % UPW) : (tid / G);
+        const int g = unit_fast ? (tid / UPW) : (tid % G);
+        const int64_t unit = ublk + ul;
+        const bool active = unit < units;
+        E* reg = lds + ul * RS;
+        const UnitGeom geo = unit_geom<LOG_NU, MODE>(unit, log_m);
+
+        // ---- gather
+        if constexpr (P == 0) {
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int r = g + G * u;          // residue; span 1 so column 0
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int64_t idx = r + (int64_t)M * i;
+                    v[u * R + i] = active ? in[geo.base_in + idx * geo.in_stride] : E{};
+                }
+            }
+        } else {
+            constexpr int PADP = PP::pad(P - 1);
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int gam = g + G * u;
+                const int r = gam & (M - 1);
+                const int q = gam >> LOGM;
+                // local index r + M i + (NU/L0) q lives in row q of the exchange
+                const int basep = r + ((NU / L0) + PADP) * q;
+#pragma unroll
+                for (int i = 0; i < R; ++i) v[u * R + i] = reg[basep + M * i];
+            }
+        }
+
+        // ---- twiddles and stages
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+            const int gam = g + G * u;
+            const int q = gam >> LOGM;            // column within the unit
+            TW tw[R];
+            if constexpr (P == 0 && MODE != MODE_ROWS) {
+#pragma unroll
+                for (int c = 1; c < R; ++c) tw[c] = lt[c];
+            } else {
+                const int qg = geo.q0 + (q << geo.log_lb);
+                const int lg0 = L0 << geo.log_lb;
+#pragma unroll
+                for (int c = 1; c < R; ++c) tw[c] = lt[qg + lg0 * c];
+            }
+            reg_pass<LR>(v + u * R, tw);
+        }
+
+        // ---- scatter
+        if constexpr (P + 1 < NP) {
+            constexpr int PAD = PP::pad(P);
+            if constexpr (P > 0) __syncthreads();   // readers of the last exchange are done
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int gam = g + G * u;
+                const int r = gam & (M - 1);
+                const int q = gam >> LOGM;
+                // local index r + M (q + L0 e) lives in row q + L0 e
+#pragma unroll
+                for (int e = 0; e < R; ++e) reg[r + (M + PAD) * (q + L0 * e)] = v[u * R + e];
+            }
+            __syncthreads();
+        } else {
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int q = g + G * u;          // M = 1: every group is a column
+#pragma unroll
+                for (int e = 0; e < R; ++e) {
+                    const int64_t idx = q + (int64_t)L0 * e;
+                    if (active) out[geo.base_out + idx * geo.out_stride] = v[u * R + e];
+                }
+            }
+        }
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, P + 1>(v, lds, lt, in, out, ublk,
+                                                                     units, log_m);
+    }
+}
+
+// in/out: element pointers (uint32_t = binary16 pair, f2_t = binary32 pair).
+// lt: level-ordered table.  units: units in this launch.  log_m: log2(N/NU),
+// the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
+// MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
+__global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E))
+fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
+                int64_t units, int log_m) {
+    static_assert(LR0 + LR1 + LR2 == LOG_NU, "radices must multiply to NU");
+    static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
+    static_assert(MODE != MODE_ROWS || LR1 > 0, "row units need two passes");
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    E* lds = reinterpret_cast<E*>(lds_raw);
+    E v[1 << LOG_E];
+    const int64_t ublk = (int64_t)blockIdx.x * UPW;
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0>(v, lds, lt, in, out, ublk, units,
+                                                             log_m);
+}
+
+}  // namespace dsfft

@@ -1,0 +1,31 @@
+// Registry of compiled kernel configurations (one entry per template
+// instantiation of fft_unit_kernel).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace dsfft {
+
+typedef hipError_t (*LaunchFn)(const void* in, void* out, const void* lt, int64_t units,
+                               int log_m, hipStream_t stream);
+
+struct KernelCfg {
+    int dtype;      // DT_F16 / DT_F32
+    int mode;       // MODE_SMALL / MODE_COLS / MODE_ROWS
+    int log_nu;     // unit size (log2)
+    int log_e;      // elements per lane (log2)
+    int upw;        // units per workgroup
+    int lr[3];      // register-pass radices (log2; 0 = absent)
+    int threads;    // workgroup size
+    size_t lds_bytes;
+    LaunchFn launch;
+    const void* func;
+};
+
+// All configurations for one dtype, in order of preference per (mode, log_nu).
+const KernelCfg* kernel_table_f16(int* count);
+const KernelCfg* kernel_table_f32(int* count);
+
+}  // namespace dsfft

@@ -1,0 +1,47 @@
+// Plan object and internal helpers shared by the C ABI translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <memory>
+#include <string>
+
+#include "kernels.hpp"
+
+namespace dsfft {
+
+struct DeviceTable {
+    void* ptr = nullptr;
+    int64_t ncap = 0;
+    size_t bytes = 0;
+    ~DeviceTable();
+};
+
+int set_error(int code, const std::string& msg);
+int hip_error(hipError_t e, const char* where);
+int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out);
+const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant);
+int count_kernels(int dtype, int mode, int log_nu);
+std::string describe(const KernelCfg* k);
+int elem_bytes(int dtype);
+
+}  // namespace dsfft
+
+struct fft_plan {
+    int64_t n = 0, batch = 0;
+    int log_n = 0, dtype = 0, kind = 0, device = 0;
+    std::shared_ptr<dsfft::DeviceTable> table;
+    const dsfft::KernelCfg* k1 = nullptr;   // single kernel, or the column kernel
+    const dsfft::KernelCfg* k2 = nullptr;   // row kernel of the two-pass schedule
+    int64_t chunk = 0;                      // transforms per two-pass chunk
+    size_t ws_need = 0, ws_bytes = 0;
+    void* ws = nullptr;
+    bool ws_owned = false;
+    hipEvent_t last = nullptr;
+    ~fft_plan();
+};
+
+namespace dsfft {
+fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants);
+int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
+}  // namespace dsfft

@@ -1,0 +1,131 @@
+// Host-side twiddle tables (Algorithm 1 of arXiv 2604.00567 and the two
+// single-factorisation baselines), generated in FP64 with the C library's
+// cos/sin, rounded once to the plan's precision, and laid out for the device.
+#include "tables.hpp"
+
+#include <cmath>
+#include <cstring>
+
+namespace dsfft {
+
+static constexpr double kEpsClamp = 1e-7;   // Linzer-Feig clamp of sin(theta)
+
+// Entry k of the size-n table in FP64.  theta = -(2 pi k)/n, w_r = cos, w_i = sin.
+//   dual-select (Algorithm 1): |w_r| >= |w_i| -> (w_r, w_i/w_r, cosine path),
+//                              else (w_i, w_r/w_i, sine path);   |ratio| <= 1.
+//   Linzer-Feig (Sec. II-B):   (w_i', w_r/w_i', sine) with w_i' = +1e-7 if |w_i| < 1e-7.
+//   cosine (Sec. II-C):        (w_r, w_i/w_r, cosine).
+//   Linzer-Feig, W^0 exempt:   k = 0 on the cosine path, the rest Linzer-Feig.
+Twiddle64 twiddle64(int64_t k, int64_t n, int kind) {
+    const double angle = -((2.0 * M_PI) * (double)k) / (double)n;
+    const double wr = std::cos(angle), wi = std::sin(angle);
+    bool cos_path;
+    switch (kind) {
+        case TABLE_DUAL_SELECT: cos_path = std::fabs(wr) >= std::fabs(wi); break;
+        case TABLE_COSINE: cos_path = true; break;
+        case TABLE_LF_W0_EXEMPT: cos_path = (k == 0); break;
+        default: cos_path = false; break;
+    }
+    Twiddle64 t;
+    if (cos_path) {
+        t.mult = wr;
+        t.ratio = wi / wr;
+        t.sine = false;
+    } else {
+        double d = wi;
+        if (kind == TABLE_LINZER_FEIG && std::fabs(d) < kEpsClamp) d = kEpsClamp;
+        t.mult = d;
+        t.ratio = wr / d;
+        t.sine = true;
+    }
+    return t;
+}
+
+// IEEE binary64 -> binary16, round to nearest, ties to even, working on the
+// bit pattern (53-bit significand shifted down to 11 or fewer bits).
+uint16_t f64_to_f16(double x) {
+    uint64_t bits;
+    std::memcpy(&bits, &x, 8);
+    const uint16_t sign = (uint16_t)((bits >> 48) & 0x8000u);
+    const int bexp = (int)((bits >> 52) & 0x7ff);
+    const uint64_t frac = bits & 0xFFFFFFFFFFFFFull;
+    if (bexp == 0x7ff) return (uint16_t)(sign | 0x7c00u | (frac ? 0x0200u : 0u));
+    if (bexp == 0) return sign;                       // FP64 subnormals are far below 2^-25
+    const int e = bexp - 1023;
+    if (e > 15) return (uint16_t)(sign | 0x7c00u);
+    const uint64_t sig = frac | (1ull << 52);
+    int drop;
+    uint32_t hexp;
+    if (e >= -14) {
+        drop = 42;
+        hexp = (uint32_t)(e + 15);
+    } else {
+        drop = 42 + (-14 - e);
+        hexp = 0;
+        if (drop > 63) return sign;
+    }
+    uint64_t q = sig >> drop;
+    const uint64_t rem = sig & ((1ull << drop) - 1);
+    const uint64_t halfway = 1ull << (drop - 1);
+    if (rem > halfway || (rem == halfway && (q & 1))) ++q;
+    uint32_t out = hexp == 0 ? (uint32_t)q : ((hexp << 10) + (uint32_t)(q - 1024));
+    if (out >= 0x7c00u) out = 0x7c00u;
+    return (uint16_t)(sign | out);
+}
+
+static inline uint32_t f32_bits(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+
+// Device entry for one twiddle (layouts in fft_device.hpp: TwH / TwF).
+static void pack_entry(const Twiddle64& t, int dtype, uint8_t* dst) {
+    if (dtype == DT_F16) {
+        const uint16_t m = f64_to_f16(t.mult);
+        const uint16_t r = f64_to_f16(t.ratio);
+        const uint16_t sm = t.sine ? (uint16_t)(m ^ 0x8000u) : m;
+        const uint32_t w = (uint32_t)sm | ((uint32_t)m << 16);
+        const uint32_t ts = (t.sine ? 16u : 0u) | ((uint32_t)r << 16);
+        std::memcpy(dst, &w, 4);
+        std::memcpy(dst + 4, &ts, 4);
+    } else {
+        const float m = (float)t.mult;
+        const float r = (float)t.ratio;
+        const float sm = t.sine ? -m : m;
+        const uint32_t mask = t.sine ? 0xFFFFFFFFu : 0u;
+        std::memcpy(dst, &sm, 4);
+        std::memcpy(dst + 4, &m, 4);
+        std::memcpy(dst + 8, &r, 4);
+        std::memcpy(dst + 12, &mask, 4);
+    }
+}
+
+size_t entry_bytes(int dtype) { return dtype == DT_F16 ? 8 : 16; }
+
+std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind) {
+    const size_t eb = entry_bytes(dtype);
+    std::vector<uint8_t> img((size_t)ncap * eb, 0);
+    for (int64_t L = 2; L <= ncap; L <<= 1)
+        for (int64_t j = 0; j < L / 2; ++j)
+            pack_entry(twiddle64(j, L, kind), dtype, img.data() + (size_t)(L / 2 + j) * eb);
+    return img;
+}
+
+void build_flat_table(int64_t n, int dtype, int kind, void* mult, void* ratio, uint8_t* path) {
+    for (int64_t k = 0; k < n / 2; ++k) {
+        const Twiddle64 t = twiddle64(k, n, kind);
+        if (dtype == DT_F16) {
+            const uint16_t m = f64_to_f16(t.mult), r = f64_to_f16(t.ratio);
+            if (mult) std::memcpy((uint8_t*)mult + 2 * k, &m, 2);
+            if (ratio) std::memcpy((uint8_t*)ratio + 2 * k, &r, 2);
+        } else {
+            const uint32_t m = f32_bits((float)t.mult), r = f32_bits((float)t.ratio);
+            if (mult) std::memcpy((uint8_t*)mult + 4 * k, &m, 4);
+            if (ratio) std::memcpy((uint8_t*)ratio + 4 * k, &r, 4);
+        }
+        if (path) path[k] = t.sine ? 1 : 0;
+    }
+}
+
+}  // namespace dsfft

@@ -1,0 +1,163 @@
+"""GPU parity: the HIP path against the oracle's emulation of the same radix-2
+Stockham pass order with six-FMA butterflies, element by element.
+
+The bar is bit equality (NaN matching NaN): every GPU butterfly computes the
+same FMAs, on the same operands, with the same table entry, as the emulation.
+The tolerances the method states (1 binary16 ulp per element per pass; 1e-6
+relative L2 in binary32 at N = 1024) are asserted as well, so a failure of
+bit equality that stays inside them is reported separately.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_00567_amd import binding, inputs
+from tests.gpu_util import mismatches, run_gpu, ulp16_diff
+
+pytestmark = pytest.mark.gpu
+
+
+def check_f16(y, ref, n):
+    finite = np.isfinite(ref) & np.isfinite(y)
+    m = int(np.log2(n))
+    assert np.all(np.isnan(y) == np.isnan(ref))
+    assert np.all(ulp16_diff(y[finite], ref[finite]) <= m)      # stated tolerance
+    assert mismatches(y, ref) == 0                                # design: bit-exact
+
+
+def check_f32(y, ref):
+    e = oracle.errors(y, ref.astype(np.float64))
+    assert e["nonfinite"] == 0 or np.all(np.isnan(y) == np.isnan(ref))
+    if e["nonfinite"] == 0:
+        assert e["rel_l2"] <= 1e-6                                # stated tolerance
+    assert mismatches(y, ref) == 0                                # design: bit-exact
+
+
+@pytest.mark.parametrize("logn", list(range(1, 17)))
+def test_fp16_dual_select_all_sizes(logn):
+    n = 1 << logn
+    batch = 37 if n <= 4096 else 3              # ragged against every units-per-workgroup
+    x = inputs.uniform(n, batch, seed=100 + logn, dtype="f16")
+    y = run_gpu(x, "f16", "dual_select")
+    check_f16(y, oracle.emulate(x, "dual_select", "f16"), n)
+
+
+@pytest.mark.parametrize("logn", list(range(1, 17)))
+def test_fp32_dual_select_all_sizes(logn):
+    n = 1 << logn
+    batch = 37 if n <= 4096 else 3
+    x = inputs.normal(n, batch, seed=200 + logn, dtype="f32")
+    y = run_gpu(x, "f32", "dual_select")
+    check_f32(y, oracle.emulate(x, "dual_select", "f32"))
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("kind", ["dual_select", "linzer_feig", "cosine", "lf_w0_exempt"])
+def test_every_table_kind_n1024(dtype, kind):
+    n, batch = 1024, 16
+    x = (inputs.uniform(n, batch, 3, "f16") if dtype == "f16" else inputs.normal(n, batch, 1, "f32"))
+    y = run_gpu(x, dtype, kind)
+    ref = oracle.emulate(x, kind, dtype)
+    assert mismatches(y, ref) == 0
+    if dtype == "f16" and kind in ("linzer_feig", "cosine"):
+        # RN16(1e7) and RN16(1.6e16) are +inf: the outputs are non-finite, as emulated
+        assert not np.all(np.isfinite(y))
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("n", [256, 1024, 2048, 4096, 8192, 16384])
+def test_every_compiled_configuration(dtype, n):
+    single, cols, rows = binding.fft_config_count(n, dtype)
+    x = inputs.uniform(n, 9, 7, dtype)
+    ref = oracle.emulate(x, "dual_select", dtype)
+    for v in range(single):
+        assert mismatches(run_gpu(x, dtype, "dual_select", variant=(v, 0, False)), ref) == 0, v
+    if cols and rows:
+        y = run_gpu(x, dtype, "dual_select", variant=(0, 0, True))
+        assert mismatches(y, ref) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_in_place(dtype):
+    for n in (1024, 1 << 15):
+        x = inputs.uniform(n, 5, 8, dtype)
+        y = run_gpu(x, dtype, "dual_select", inplace=True)
+        assert mismatches(y, oracle.emulate(x, "dual_select", dtype)) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_largest_size(dtype):
+    n = 1 << 20
+    x = inputs.tones(n, 2, 33, dtype)
+    y = run_gpu(x, dtype, "dual_select")
+    assert mismatches(y, oracle.emulate(x, "dual_select", dtype)) == 0
+
+
+def test_special_values_fp16():
+    n, batch = 1024, 8
+    x = inputs.uniform(n, batch, 9, "f16")
+    flat = x.reshape(-1)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(flat.size, 64, replace=False)
+    flat[idx[:8]] = np.inf
+    flat[idx[8:16]] = -np.inf
+    flat[idx[16:24]] = np.nan
+    flat[idx[24:40]] = np.float16(2.0 ** -24) * rng.integers(-1023, 1024, 16)   # subnormals
+    flat[idx[40:48]] = np.float16(65504.0)
+    flat[idx[48:64]] = np.float16(-0.0)
+    x[0] = 0.0                                                                  # an all-zero transform
+    x[1] = np.float16(2.0 ** -24)                                               # all smallest subnormal
+    y = run_gpu(x, "f16", "dual_select")
+    assert mismatches(y, oracle.emulate(x, "dual_select", "f16")) == 0
+
+
+def test_fp32_subnormals_kept():
+    n, batch = 256, 4
+    x = (inputs.normal(n, batch, 10, "f32") * np.float32(1e-39)).astype(np.float32)
+    y = run_gpu(x, "f32", "dual_select")
+    assert mismatches(y, oracle.emulate(x, "dual_select", "f32")) == 0
+    assert np.any(y != 0)
+
+
+def test_batch_one_and_smallest_n():
+    for n in (2, 4, 1024):
+        x = inputs.uniform(n, 1, 11, "f16")
+        assert mismatches(run_gpu(x, "f16", "dual_select"), oracle.emulate(x, "dual_select", "f16")) == 0
+
+
+@pytest.mark.parametrize("n,batch,samples", [(1024, 65536, 48), (4096, 16384, 24)])
+def test_full_size_sampled(n, batch, samples):
+    """Batched FP16 fixed-size workload at full size; sampled transforms are
+    checked one by one against the emulation, all of them against FP64 bounds."""
+    x = inputs.uniform(n, batch, seed=2, dtype="f16")
+    y = run_gpu(x, "f16", "dual_select")
+    pick = np.random.default_rng(5).choice(batch, samples, replace=False)
+    pick = np.concatenate([pick, [0, batch - 1]])
+    ref = oracle.emulate(x[pick], "dual_select", "f16")
+    assert mismatches(y[pick], ref) == 0
+    e = oracle.errors(y[pick], oracle.fft64(x[pick].astype(np.float64)))
+    assert e["nonfinite"] == 0 and e["rel_l2"] < (1 + 2.0 ** -11) ** int(np.log2(n)) - 1
+    assert np.all(np.isfinite(y))
+
+
+def test_argument_errors():
+    torch = pytest.importorskip("torch")
+    n, batch = 1024, 4
+    plan = binding.fft_plan_create(n, batch, "f16", "dual_select")
+    try:
+        x = torch.zeros((batch * n * 2 + 8,), dtype=torch.float16, device="cuda:0")
+        base = x.data_ptr()
+        with pytest.raises(binding.FFTError) as e:
+            binding.fft_execute(plan, base + 2, base + 2)          # misaligned
+        assert e.value.code == binding.FFT_EINVAL
+        with pytest.raises(binding.FFTError) as e:
+            binding.fft_execute(plan, base, base + 8)              # partial overlap
+        assert e.value.code == binding.FFT_EINVAL
+        with pytest.raises(binding.FFTError) as e:
+            binding.fft_execute(plan, 0, base)
+        assert e.value.code == binding.FFT_EINVAL
+    finally:
+        binding.fft_destroy(plan)
+    for bad in ((1000, 1), (1 << 21, 1), (1024, 0)):
+        with pytest.raises(binding.FFTError):
+            binding.fft_plan_create(bad[0], bad[1], "f16", "dual_select")

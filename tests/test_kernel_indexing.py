@@ -1,0 +1,225 @@
+"""CPU simulation of the FFT kernel's per-lane index arithmetic (no GPU).
+
+Replays, lane by lane, the addressing of fft_unit_kernel for every compiled
+configuration: global loads/stores, the padded LDS exchange between register
+passes, and the twiddle entries, with FP64 butterflies.  It checks that every
+access stays inside its buffer, that each output is written exactly once, that
+each LDS read sees a value written in the same exchange, and that the result is
+the DFT.  This guards the index math before it runs on the GPU.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+CONFIGS = os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                       "paper_2604_00567_amd", "csrc", "configs.inc")
+MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
+
+
+def load_configs():
+    out = []
+    for line in open(CONFIGS):
+        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", line)
+        if m:
+            mode = MODES[m.group(1)]
+            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 8)))
+    return out
+
+
+class PassPlan:
+    def __init__(self, log_nu, lrs):
+        self.log_nu = log_nu
+        self.lrs = [x for x in lrs if x]
+        self.np = len(self.lrs)
+
+    def lr(self, p):
+        return self.lrs[p]
+
+    def log_l0(self, p):
+        return sum(self.lrs[:p])
+
+    def log_m(self, p):
+        return self.log_nu - self.log_l0(p) - self.lr(p)
+
+    def pad(self, p):
+        return (1 << self.log_m(p + 1)) if (p + 1 < self.np and self.log_m(p + 1) < 5) else 0
+
+    def padded(self, p):
+        return (1 << self.log_nu) + ((1 << self.log_nu) >> self.log_m(p)) * self.pad(p)
+
+    def region(self):
+        r = 1 << self.log_nu
+        for p in range(self.np - 1):
+            r = max(r, self.padded(p))
+        return r | 1
+
+
+def level_twiddle(idx):
+    """Entry idx of the level-ordered table: L/2 + j -> W_L^j."""
+    L = 1
+    while L <= idx:
+        L <<= 1
+    j = idx - L // 2
+    return np.exp(-2j * np.pi * j / L), L, j
+
+
+def bfly(a, b, w):
+    return a + w * b, a - w * b
+
+
+def simulate(cfg, n, batch, x=None):
+    mode, log_nu, log_e, upw, lr0, lr1, lr2 = cfg
+    pp = PassPlan(log_nu, (lr0, lr1, lr2))
+    NU, EL = 1 << log_nu, 1 << log_e
+    G = NU // EL
+    NT = upw * G
+    RS = pp.region()
+    log_m = (n.bit_length() - 1) - log_nu
+    units = batch if mode == 0 else batch << log_m
+    if x is None:
+        rng = np.random.default_rng(cfg[1] * 7 + cfg[3])
+        x = rng.standard_normal(batch * n) + 1j * rng.standard_normal(batch * n)
+    out = np.full(batch * n, np.nan + 0j)
+    written = np.zeros(batch * n, int)
+    tcap = max(n, 4096)
+    grid = (units + upw - 1) // upw
+    for blk in range(grid):
+        lds = np.full(upw * RS, np.nan + 0j)
+        lds_gen = np.full(upw * RS, -1)
+        v = np.zeros((NT, EL), complex)
+        for p in range(pp.np):
+            LR = pp.lr(p)
+            R = 1 << LR
+            L0 = 1 << pp.log_l0(p)
+            LOGM = pp.log_m(p)
+            M = 1 << LOGM
+            GPL = EL // R
+            unit_fast = mode == 1 or (mode == 2 and p == pp.np - 1)
+            newv = np.zeros_like(v)
+            geos = []
+            for tid in range(NT):
+                ul = tid % upw if unit_fast else tid // G
+                g = tid // upw if unit_fast else tid % G
+                unit = blk * upw + ul
+                active = unit < units
+                reg = ul * RS
+                if mode == 0:
+                    base_in = base_out = unit << log_nu
+                    in_s = out_s = 1
+                    q0, log_lb = 0, 0
+                elif mode == 1:
+                    b, r0 = unit >> log_m, unit & ((1 << log_m) - 1)
+                    base_in = base_out = (b << (log_m + log_nu)) + r0
+                    in_s = out_s = 1 << log_m
+                    q0, log_lb = 0, 0
+                else:
+                    b, q0 = unit >> log_m, unit & ((1 << log_m) - 1)
+                    log_lb = log_m
+                    base_in = (b << (log_m + log_nu)) + (q0 << log_nu)
+                    base_out = (b << (log_m + log_nu)) + q0
+                    in_s, out_s = 1, 1 << log_m
+                vv = v[tid].copy() if p > 0 else np.zeros(EL, complex)
+                # gather
+                for u in range(GPL):
+                    gam = g + G * u
+                    if p == 0:
+                        r = gam
+                        for i in range(R):
+                            idx = r + M * i
+                            assert idx < NU
+                            if active:
+                                a = base_in + idx * in_s
+                                assert 0 <= a < batch * n
+                                vv[u * R + i] = x[a]
+                    else:
+                        padp = pp.pad(p - 1)
+                        r, q = gam & (M - 1), gam >> LOGM
+                        basep = r + ((NU // L0) + padp) * q
+                        for i in range(R):
+                            a = reg + basep + M * i
+                            assert reg <= a < reg + RS and basep + M * i < RS
+                            assert lds_gen[a] == p - 1, "LDS read of a slot not written"
+                            vv[u * R + i] = lds[a]
+                # stages
+                for u in range(GPL):
+                    gam = g + G * u
+                    q = gam >> LOGM
+                    if p == 0 and mode != 2:
+                        tw_idx = [c for c in range(R)]
+                    else:
+                        qg = q0 + (q << log_lb)
+                        lg0 = L0 << log_lb
+                        tw_idx = [qg + lg0 * c for c in range(R)]
+                    grp = vv[u * R:(u + 1) * R].copy()
+                    for t in range(1, LR + 1):
+                        H = R >> t
+                        nv = np.zeros(R, complex)
+                        for e in range(1 << (t - 1)):
+                            c = (1 << (t - 1)) + e
+                            assert 0 < tw_idx[c] < tcap
+                            w, L, j = level_twiddle(tw_idx[c])
+                            # the twiddle must be W_{L}^{j} with L the global span
+                            assert L == (L0 << log_lb) * (1 << t) and j < L // 2
+                            for i in range(H):
+                                A, B = bfly(grp[i + 2 * H * e], grp[i + H + 2 * H * e], w)
+                                nv[i + H * e] = A
+                                nv[i + H * e + R // 2] = B
+                        grp = nv
+                    vv[u * R:(u + 1) * R] = grp
+                newv[tid] = vv
+                geos.append((ul, g, active, reg, base_out, out_s))
+            # every lane has gathered before any lane scatters (the kernel's barrier)
+            for tid in range(NT):
+                ul, g, active, reg, base_out, out_s = geos[tid]
+                vv = newv[tid]
+                if p + 1 < pp.np:
+                    pad = pp.pad(p)
+                    for u in range(GPL):
+                        gam = g + G * u
+                        r, q = gam & (M - 1), gam >> LOGM
+                        for e in range(R):
+                            a = reg + r + (M + pad) * (q + L0 * e)
+                            assert reg <= a < reg + RS
+                            assert lds_gen[a] < p, "two writes to one LDS slot"
+                            lds[a] = vv[u * R + e]
+                            lds_gen[a] = p
+                else:
+                    for u in range(GPL):
+                        q = g + G * u
+                        for e in range(R):
+                            idx = q + L0 * e
+                            assert idx < NU
+                            if active:
+                                a = base_out + idx * out_s
+                                assert 0 <= a < batch * n
+                                out[a] = vv[u * R + e]
+                                written[a] += 1
+            v = newv
+    return x, out, written, units
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_configs() if c[0] == 0])
+def test_small_configs_index_math(cfg):
+    n = 1 << cfg[1]
+    batch = cfg[3] + 1                            # ragged tail: one extra unit
+    x, out, written, _ = simulate(cfg, n, batch)
+    assert np.all(written == 1)
+    ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+@pytest.mark.parametrize("m1,m2", [(6, 6), (7, 6), (7, 7), (8, 6)])
+def test_two_pass_index_math(m1, m2):
+    cfgs = load_configs()
+    cols = next(c for c in cfgs if c[0] == 1 and c[1] == m1)
+    rows = next(c for c in cfgs if c[0] == 2 and c[1] == m2)
+    n = 1 << (m1 + m2)
+    batch = 2
+    x, ws, w1, _ = simulate(cols, n, batch)
+    assert np.all(w1 == 1)
+    _, out, w2, _ = simulate(rows, n, batch, x=ws)
+    assert np.all(w2 == 1)
+    ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n

@@ -1,0 +1,67 @@
+"""CPU-side checks of the HIP library: it loads, exports every function the
+header declares, its host-built tables equal the oracle's bit for bit, and its
+argument validation rejects bad requests before touching a GPU."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_00567_amd import binding
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(binding.LIB_PATH)
+    names = binding.declared_functions()
+    assert "fft_plan_create" in names and "fft_execute" in names and "fft_destroy" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("kind", ["dual_select", "linzer_feig", "cosine", "lf_w0_exempt"])
+def test_host_tables_match_oracle(dtype, kind):
+    view = np.uint16 if dtype == "f16" else np.uint32
+    for m in (1, 2, 3, 5, 8, 10, 12, 16, 20):
+        n = 1 << m
+        m_lib, r_lib, p_lib = binding.fft_table_build(n, dtype, kind)
+        m_orc, r_orc, p_orc = oracle.rounded_table(n, kind, dtype)
+        assert np.array_equal(m_lib.view(view), m_orc.view(view)), n
+        assert np.array_equal(r_lib.view(view), r_orc.view(view)), n
+        assert np.array_equal(p_lib, p_orc.astype(np.uint8)), n
+
+
+def test_dual_select_table_facts_in_storage_precision():
+    # Table I: at N = 1024 the stored dual-select ratio peaks at exactly 1.0,
+    # the paths split 256 / 256, and the clamped Linzer-Feig entry overflows binary16
+    for dtype in ("f16", "f32"):
+        m, r, p = binding.fft_table_build(1024, dtype, "dual_select")
+        assert float(np.max(np.abs(r.astype(np.float64)))) == 1.0
+        assert int(np.sum(p == 0)) == 256 and int(np.sum(p == 1)) == 256
+    m, r, p = binding.fft_table_build(1024, "f16", "linzer_feig")
+    assert np.isinf(r[0]) and np.all(p == 1)
+
+
+def test_argument_validation_without_gpu():
+    for n in (0, 1, 3, 1000, 1 << 21):
+        with pytest.raises(binding.FFTError) as e:
+            binding.fft_table_build(n, "f16", "dual_select")
+        assert e.value.code == binding.FFT_EINVAL
+        with pytest.raises(binding.FFTError):
+            binding.fft_plan_create(n, 1, "f16", "dual_select")
+        assert "power of two" in binding.fft_last_error()
+    with pytest.raises(binding.FFTError):
+        binding.fft_plan_create(1024, 0, "f16", "dual_select")
+    assert "batch" in binding.fft_last_error()
+    with pytest.raises(binding.FFTError):
+        binding.fft_table_build(1024, 7, "dual_select")
+    with pytest.raises(binding.FFTError):
+        binding.fft_table_build(1024, "f16", 9)
+    binding.fft_destroy(None)   # NULL-safe
+
+
+def test_compiled_configurations_cover_every_size():
+    for dtype in ("f16", "f32"):
+        for m in range(1, 21):
+            single, cols, rows = binding.fft_config_count(1 << m, dtype)
+            assert single > 0 or (cols > 0 and rows > 0), (dtype, m)
