@@ -33,6 +33,12 @@ class FFTError(RuntimeError):
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2604_00567_amd.build`")
 
+# torch bundles its own HIP runtime under the same soname (libamdhip64.so.7).
+# Loading torch first makes the library bind to that runtime, so streams and
+# device pointers handed over from torch belong to the runtime the kernels are
+# launched with; loading the library first would bring in a second runtime.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i64, _int, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
 _SIGS = {

@@ -75,9 +75,12 @@ __device__ __forceinline__ void bfly(uint32_t& a, uint32_t& b, const TwH tw) {
 
 // Six-FMA butterfly, binary32 (six v_fma_f32); the path picks (c_r, c_i) from
 // (b_r, b_i) or (b_i, b_r) with a bitwise select on the table's lane mask.
+// (The vector elements are copied to scalars before the bit casts: clang's
+// __builtin_bit_cast applied directly to an ext_vector element reads element 0.)
 __device__ __forceinline__ void bfly(f2_t& a, f2_t& b, const TwF tw) {
-    const uint32_t br = __builtin_bit_cast(uint32_t, b.x);
-    const uint32_t bi = __builtin_bit_cast(uint32_t, b.y);
+    const float bxf = b.x, byf = b.y;
+    const uint32_t br = __builtin_bit_cast(uint32_t, bxf);
+    const uint32_t bi = __builtin_bit_cast(uint32_t, byf);
     const float cr = __builtin_bit_cast(float, (tw.mask & bi) | (~tw.mask & br));
     const float ci = __builtin_bit_cast(float, (tw.mask & br) | (~tw.mask & bi));
     const float s1 = __builtin_fmaf(-tw.t, ci, cr);
@@ -221,14 +224,19 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 
         // ---- gather
         if constexpr (P == 0) {
+            if (active) {
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int r = g + G * u;          // residue; span 1 so column 0
+                for (int u = 0; u < GPL; ++u) {
+                    const int r = g + G * u;      // residue; span 1 so column 0
 #pragma unroll
-                for (int i = 0; i < R; ++i) {
-                    const int64_t idx = r + (int64_t)M * i;
-                    v[u * R + i] = active ? in[geo.base_in + idx * geo.in_stride] : E{};
+                    for (int i = 0; i < R; ++i) {
+                        const int64_t idx = r + (int64_t)M * i;
+                        v[u * R + i] = in[geo.base_in + idx * geo.in_stride];
+                    }
                 }
+            } else {
+#pragma unroll
+                for (int k = 0; k < EL; ++k) v[k] = E{};
             }
         } else {
             constexpr int PADP = PP::pad(P - 1);
@@ -277,13 +285,15 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
             }
             __syncthreads();
         } else {
+            if (active) {
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int q = g + G * u;          // M = 1: every group is a column
+                for (int u = 0; u < GPL; ++u) {
+                    const int q = g + G * u;      // M = 1: every group is a column
 #pragma unroll
-                for (int e = 0; e < R; ++e) {
-                    const int64_t idx = q + (int64_t)L0 * e;
-                    if (active) out[geo.base_out + idx * geo.out_stride] = v[u * R + e];
+                    for (int e = 0; e < R; ++e) {
+                        const int64_t idx = q + (int64_t)L0 * e;
+                        out[geo.base_out + idx * geo.out_stride] = v[u * R + e];
+                    }
                 }
             }
         }

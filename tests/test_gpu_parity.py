@@ -17,7 +17,16 @@ from tests.gpu_util import mismatches, run_gpu, ulp16_diff
 pytestmark = pytest.mark.gpu
 
 
+def describe_mismatch(y, ref, limit=6):
+    bad = np.argwhere(~((y.view(np.uint16 if y.dtype == np.float16 else np.uint32) ==
+                         ref.view(np.uint16 if ref.dtype == np.float16 else np.uint32)) |
+                        (np.isnan(y) & np.isnan(ref))))
+    return "; ".join(f"{tuple(i)}: gpu={y[tuple(i)]!r} oracle={ref[tuple(i)]!r}" for i in bad[:limit])
+
+
 def check_f16(y, ref, n):
+    print(f"check n={n} shape={y.shape} mismatches={mismatches(y, ref)} "
+          f"{describe_mismatch(y, ref)}", flush=True)
     finite = np.isfinite(ref) & np.isfinite(y)
     m = int(np.log2(n))
     assert np.all(np.isnan(y) == np.isnan(ref))

@@ -65,3 +65,10 @@ def test_compiled_configurations_cover_every_size():
         for m in range(1, 21):
             single, cols, rows = binding.fft_config_count(1 << m, dtype)
             assert single > 0 or (cols > 0 and rows > 0), (dtype, m)
+
+
+def test_single_hip_runtime_in_process():
+    # the binding loads torch first so the library shares torch's HIP runtime
+    with open("/proc/self/maps") as f:
+        paths = {line.split()[-1] for line in f if "libamdhip64" in line}
+    assert len(paths) == 1, paths
