@@ -91,6 +91,15 @@ const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant) {
     return nullptr;
 }
 
+// First configuration of (dtype, mode, log_nu) that does not stage through
+// LDS with 16-byte accesses (used when data pointers are not 16-byte aligned).
+const KernelCfg* find_plain_kernel(int dtype, int mode, int log_nu) {
+    for (int v = 0;; ++v) {
+        const KernelCfg* k = find_kernel(dtype, mode, log_nu, v);
+        if (!k || !k->staged) return k;
+    }
+}
+
 int count_kernels(int dtype, int mode, int log_nu) {
     int n = 0;
     while (find_kernel(dtype, mode, log_nu, n)) ++n;
@@ -101,9 +110,9 @@ std::string describe(const KernelCfg* k) {
     if (!k) return "none";
     static const char* modes[] = {"small", "cols", "rows"};
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],t=%d,lds=%zu",
+    std::snprintf(buf, sizeof buf, "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],stg=%d,t=%d,lds=%zu",
                   modes[k->mode], k->log_nu, k->log_e, k->upw, k->lr[0], k->lr[1], k->lr[2],
-                  k->threads, k->lds_bytes);
+                  k->staged, k->threads, k->lds_bytes);
     return buf;
 }
 
@@ -115,12 +124,14 @@ int choose_schedule(fft_plan* p, const int* variants) {
     const int v0 = variants ? variants[0] : 0, v1 = variants ? variants[1] : 0;
     if (m <= small_limit(p->dtype) && (!variants || variants[2] == 0)) {
         p->k1 = find_kernel(p->dtype, MODE_SMALL, m, v0);
+        p->k1_plain = find_plain_kernel(p->dtype, MODE_SMALL, m);
         p->k2 = nullptr;
-        if (!p->k1) return set_error(FFT_EUNSUPPORTED, "no kernel for this size");
+        if (!p->k1 || !p->k1_plain) return set_error(FFT_EUNSUPPORTED, "no kernel for this size");
         return FFT_OK;
     }
     const int m1 = (m + 1) / 2, m2 = m - m1;     // columns of 2^m1, rows of 2^m2
     p->k1 = find_kernel(p->dtype, MODE_COLS, m1, v0);
+    p->k1_plain = p->k1;
     p->k2 = find_kernel(p->dtype, MODE_ROWS, m2, v1);
     if (!p->k1 || !p->k2) return set_error(FFT_EUNSUPPORTED, "no two-pass kernels for this size");
     return FFT_OK;
@@ -148,7 +159,9 @@ void size_workspace(fft_plan* p) {
 int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
     const void* lt = p->table->ptr;
     if (!p->k2) {
-        hipError_t e = p->k1->launch(in, out, lt, p->batch, 0, s);
+        const bool aligned16 = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
+        const KernelCfg* k = (p->k1->staged && !aligned16) ? p->k1_plain : p->k1;
+        hipError_t e = k->launch(in, out, lt, p->batch, 0, s);
         if (e != hipSuccess) return hip_error(e, "launch");
         return FFT_OK;
     }

@@ -193,9 +193,47 @@ __device__ __forceinline__ UnitGeom unit_geom(int64_t unit, int log_m) {
     return u;
 }
 
+// 16-byte vector used for staged global <-> LDS copies.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+// Copies elements [first, first + count) of `in` into lds[0, count) with
+// 16-byte non-temporal loads (count and first are multiples of 16 bytes;
+// the global pointer is 16-byte aligned), then waits for the whole block.
+template <class E, int NT, int CAP>
+__device__ __forceinline__ void stage_in(const E* in, E* lds, int64_t first, int64_t count) {
+    constexpr int VEC = 16 / (int)sizeof(E);
+    static_assert(CAP % (VEC * NT) == 0, "block must split into 16-byte vectors per thread");
+    const u32x4_t* src = reinterpret_cast<const u32x4_t*>(in + first);
+    u32x4_t* dst = reinterpret_cast<u32x4_t*>(lds);
+    const int nvec = (int)(count / VEC);
+#pragma unroll
+    for (int k = 0; k < CAP / VEC / NT; ++k) {
+        const int j = k * NT + (int)threadIdx.x;
+        if (j < nvec) dst[j] = __builtin_nontemporal_load(src + j);
+    }
+    __syncthreads();
+}
+
+// Copies lds[0, count) to elements [first, first + count) of `out` with
+// 16-byte non-temporal stores.
+template <class E, int NT, int CAP>
+__device__ __forceinline__ void stage_out(const E* lds, E* out, int64_t first, int64_t count) {
+    constexpr int VEC = 16 / (int)sizeof(E);
+    static_assert(CAP % (VEC * NT) == 0, "block must split into 16-byte vectors per thread");
+    const u32x4_t* src = reinterpret_cast<const u32x4_t*>(lds);
+    u32x4_t* dst = reinterpret_cast<u32x4_t*>(out + first);
+    const int nvec = (int)(count / VEC);
+#pragma unroll
+    for (int k = 0; k < CAP / VEC / NT; ++k) {
+        const int j = k * NT + (int)threadIdx.x;
+        if (j < nvec) __builtin_nontemporal_store(src[j], dst + j);
+    }
+}
+
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
 // LR radix-2 stages per group, scatter (LDS or global).
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int P>
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int P>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                           const E* in, E* out, int64_t ublk, int64_t units,
                                           int log_m) {
@@ -213,6 +251,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr int LOGM = PP::log_m(P);
         constexpr int M = 1 << LOGM;
         constexpr int GPL = EL / R;
+        constexpr int NT_OF = UPW * G;
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
         const int tid = threadIdx.x;
         const int ul = unit_fast ? (tid % UPW) : (tid / G);
@@ -223,7 +262,20 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         const UnitGeom geo = unit_geom<LOG_NU, MODE>(unit, log_m);
 
         // ---- gather
-        if constexpr (P == 0) {
+        if constexpr (P == 0 && STG) {
+            // The workgroup's units are contiguous in memory: copy the block
+            // into LDS (natural order) with 16-byte streaming loads, then
+            // gather the pass's decimated groups from LDS.
+            stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, ublk << LOG_NU,
+                                              (units - ublk < UPW ? units - ublk : UPW) << LOG_NU);
+            const E* nat = lds + ul * NU;
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int r = g + G * u;
+#pragma unroll
+                for (int i = 0; i < R; ++i) v[u * R + i] = nat[r + M * i];
+            }
+        } else if constexpr (P == 0) {
             if (active) {
 #pragma unroll
                 for (int u = 0; u < GPL; ++u) {
@@ -231,7 +283,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                     for (int i = 0; i < R; ++i) {
                         const int64_t idx = r + (int64_t)M * i;
-                        v[u * R + i] = in[geo.base_in + idx * geo.in_stride];
+                        v[u * R + i] = __builtin_nontemporal_load(in + geo.base_in + idx * geo.in_stride);
                     }
                 }
             } else {
@@ -273,7 +325,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         // ---- scatter
         if constexpr (P + 1 < NP) {
             constexpr int PAD = PP::pad(P);
-            if constexpr (P > 0) __syncthreads();   // readers of the last exchange are done
+            if constexpr (P > 0 || STG) __syncthreads();   // readers of LDS are done
 #pragma unroll
             for (int u = 0; u < GPL; ++u) {
                 const int gam = g + G * u;
@@ -284,6 +336,19 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 for (int e = 0; e < R; ++e) reg[r + (M + PAD) * (q + L0 * e)] = v[u * R + e];
             }
             __syncthreads();
+        } else if constexpr (STG) {
+            // outputs to LDS in natural order, then 16-byte streaming stores
+            __syncthreads();                      // every lane is done reading LDS
+            E* nat = lds + ul * NU;
+#pragma unroll
+            for (int u = 0; u < GPL; ++u) {
+                const int q = g + G * u;
+#pragma unroll
+                for (int e = 0; e < R; ++e) nat[q + L0 * e] = v[u * R + e];
+            }
+            __syncthreads();
+            stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, ublk << LOG_NU,
+                                               (units - ublk < UPW ? units - ublk : UPW) << LOG_NU);
         } else {
             if (active) {
 #pragma unroll
@@ -292,13 +357,13 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                     for (int e = 0; e < R; ++e) {
                         const int64_t idx = q + (int64_t)L0 * e;
-                        out[geo.base_out + idx * geo.out_stride] = v[u * R + e];
+                        __builtin_nontemporal_store(v[u * R + e], out + geo.base_out + idx * geo.out_stride);
                     }
                 }
             }
         }
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, P + 1>(v, lds, lt, in, out, ublk,
-                                                                     units, log_m);
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, P + 1>(v, lds, lt, in, out,
+                                                                          ublk, units, log_m);
     }
 }
 
@@ -306,19 +371,20 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // lt: level-ordered table.  units: units in this launch.  log_m: log2(N/NU),
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG>
 __global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E))
 fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
     static_assert(LR0 + LR1 + LR2 == LOG_NU, "radices must multiply to NU");
     static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
     static_assert(MODE != MODE_ROWS || LR1 > 0, "row units need two passes");
+    static_assert(STG == 0 || MODE == MODE_SMALL, "staging needs contiguous units");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     E v[1 << LOG_E];
     const int64_t ublk = (int64_t)blockIdx.x * UPW;
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0>(v, lds, lt, in, out, ublk, units,
-                                                             log_m);
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, 0>(v, lds, lt, in, out, ublk,
+                                                                  units, log_m);
 }
 
 }  // namespace dsfft

@@ -18,6 +18,7 @@ struct KernelCfg {
     int log_e;      // elements per lane (log2)
     int upw;        // units per workgroup
     int lr[3];      // register-pass radices (log2; 0 = absent)
+    int staged;     // 1: block copied through LDS with 16-byte accesses
     int threads;    // workgroup size
     size_t lds_bytes;
     LaunchFn launch;

@@ -6,7 +6,7 @@
 
 namespace dsfft {
 
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG>
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
     using TW = typename TwOf<E>::type;
@@ -15,17 +15,17 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
     const int64_t grid = (units + UPW - 1) / UPW;
     if (grid <= 0) return hipSuccess;
     if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((fft_unit_kernel<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2>),
+    hipLaunchKernelGGL((fft_unit_kernel<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG>),
                        dim3((unsigned)grid), dim3(NT), LDS, stream, (const E*)in, (E*)out,
                        (const TW*)lt, units, log_m);
     return hipGetLastError();
 }
 
-#define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2)                                          \
-    {DTYPE_ID, MODE, LOG_NU, LOG_E, UPW, {LR0, LR1, LR2}, (UPW) << ((LOG_NU) - (LOG_E)),       \
+#define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG)                                     \
+    {DTYPE_ID, MODE, LOG_NU, LOG_E, UPW, {LR0, LR1, LR2}, STG, (UPW) << ((LOG_NU) - (LOG_E)),  \
      (size_t)(UPW) * PassPlan<LOG_NU, LR0, LR1, LR2>::region() * sizeof(ELEM_T),               \
-     &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2>,                            \
-     (const void*)&fft_unit_kernel<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2>},
+     &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG>,                       \
+     (const void*)&fft_unit_kernel<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG>},
 
 static const KernelCfg kTable[] = {
 #include "configs.inc"

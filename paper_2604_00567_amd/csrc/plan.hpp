@@ -32,6 +32,7 @@ struct fft_plan {
     int log_n = 0, dtype = 0, kind = 0, device = 0;
     std::shared_ptr<dsfft::DeviceTable> table;
     const dsfft::KernelCfg* k1 = nullptr;   // single kernel, or the column kernel
+    const dsfft::KernelCfg* k1_plain = nullptr;  // k1's size without 16-byte staging
     const dsfft::KernelCfg* k2 = nullptr;   // row kernel of the two-pass schedule
     int64_t chunk = 0;                      // transforms per two-pass chunk
     size_t ws_need = 0, ws_bytes = 0;

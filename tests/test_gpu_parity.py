@@ -170,3 +170,28 @@ def test_argument_errors():
     for bad in ((1000, 1), (1 << 21, 1), (1024, 0)):
         with pytest.raises(binding.FFTError):
             binding.fft_plan_create(bad[0], bad[1], "f16", "dual_select")
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_unaligned_pointers_use_plain_kernel(dtype):
+    """Element-aligned but not 16-byte aligned data takes the unstaged kernel."""
+    torch = pytest.importorskip("torch")
+    n, batch = 1024, 6
+    x = inputs.uniform(n, batch, 12, dtype)
+    eb = 4 if dtype == "f16" else 8
+    tdt = torch.float16 if dtype == "f16" else torch.float32
+    per = eb // (2 if dtype == "f16" else 4)          # storage values per element (2)
+    buf_in = torch.zeros(n * batch * 2 + 16, dtype=tdt, device="cuda:0")
+    buf_out = torch.zeros_like(buf_in)
+    off = per                                          # one element: 4 or 8 bytes
+    buf_in[off:off + n * batch * 2] = torch.from_numpy(x.reshape(-1)).to("cuda:0")
+    plan = binding.fft_plan_create(n, batch, dtype, "dual_select")
+    try:
+        binding.fft_execute(plan, buf_in.data_ptr() + off * buf_in.element_size(),
+                            buf_out.data_ptr() + off * buf_out.element_size(),
+                            torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    finally:
+        binding.fft_destroy(plan)
+    y = buf_out[off:off + n * batch * 2].cpu().numpy().reshape(batch, n, 2)
+    assert mismatches(y, oracle.emulate(x, "dual_select", dtype)) == 0

@@ -21,10 +21,11 @@ MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
 def load_configs():
     out = []
     for line in open(CONFIGS):
-        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)", line)
+        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)",
+                     line)
         if m:
             mode = MODES[m.group(1)]
-            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 8)))
+            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 9)))
     return out
 
 
@@ -70,7 +71,7 @@ def bfly(a, b, w):
 
 
 def simulate(cfg, n, batch, x=None):
-    mode, log_nu, log_e, upw, lr0, lr1, lr2 = cfg
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg = cfg
     pp = PassPlan(log_nu, (lr0, lr1, lr2))
     NU, EL = 1 << log_nu, 1 << log_e
     G = NU // EL
@@ -124,7 +125,17 @@ def simulate(cfg, n, batch, x=None):
                 # gather
                 for u in range(GPL):
                     gam = g + G * u
-                    if p == 0:
+                    if p == 0 and stg:
+                        # staged: the block sits in LDS in natural order
+                        assert mode == 0 and EL * 4 >= 16
+                        r = gam
+                        for i in range(R):
+                            idx = r + M * i
+                            a = ul * NU + idx
+                            assert a < upw * NU <= upw * RS
+                            if active:
+                                vv[u * R + i] = x[base_in + idx]
+                    elif p == 0:
                         r = gam
                         for i in range(R):
                             idx = r + M * i
@@ -191,6 +202,8 @@ def simulate(cfg, n, batch, x=None):
                         for e in range(R):
                             idx = q + L0 * e
                             assert idx < NU
+                            if stg:
+                                assert ul * NU + idx < upw * NU <= upw * RS
                             if active:
                                 a = base_out + idx * out_s
                                 assert 0 <= a < batch * n
@@ -215,6 +228,7 @@ def test_two_pass_index_math(m1, m2):
     cfgs = load_configs()
     cols = next(c for c in cfgs if c[0] == 1 and c[1] == m1)
     rows = next(c for c in cfgs if c[0] == 2 and c[1] == m2)
+    assert cols[-1] == 0 and rows[-1] == 0
     n = 1 << (m1 + m2)
     batch = 2
     x, ws, w1, _ = simulate(cols, n, batch)
