@@ -61,6 +61,8 @@ typedef enum {
 } fft_table_kind;
 
 typedef struct fft_plan fft_plan;     /* opaque; immutable after creation   */
+typedef struct fft_batch fft_batch;   /* opaque uneven-size batch plan      */
+typedef struct fft_serve_slot fft_serve_slot;   /* one in-flight serving launch */
 
 /* Message for the last error on this thread ("" if none).  Never NULL. */
 const char* fft_last_error(void);
@@ -127,6 +129,73 @@ fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft
 /* Number of compiled configurations for (n, dtype): *single for the
  * one-kernel schedule, *cols and *rows for the two kernels of the two-pass one. */
 int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows);
+
+/*
+ * Uneven-size batch: `count` transforms with sizes n[i] (powers of two,
+ * 2 .. 2^18), packed back to back in the order given (transform i starts at
+ * element sum_{j<i} n[j]).  Every transform is computed exactly as
+ * fft_plan_create would (same butterflies, same table), but all of them run
+ * in one persistent work-queue kernel launch: sizes up to 2^13 as whole-
+ * transform work items, 2^14 .. 2^18 as column items then row items of the
+ * two-pass schedule, ordered through per-transform counters in device memory.
+ * The launch (a control-block clear plus the kernel) is captured once in a
+ * HIP graph and replayed by every execute; new data pointers are patched into
+ * the captured kernel node.  The batch owns a workspace of sum of the sizes
+ * >= 2^14 elements.  Returns NULL on error.
+ */
+fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, fft_table_kind kind);
+
+/* Same, with the tuner's choice per size class: choice_1024 / choice_4096
+ * select the alternative configuration (0 or 1) for N = 2^10 / 2^12. */
+fft_batch* fft_batch_create_tuned(const int64_t* n, int64_t count, fft_dtype dtype,
+                                  fft_table_kind kind, int choice_1024, int choice_4096);
+
+/* Enqueues the whole uneven batch on `stream` (device pointers, packed
+ * layout, element-aligned; in == out allowed).  Async. */
+int fft_batch_execute(fft_batch* batch, const void* in, void* out, void* stream);
+
+/* Total elements of the packed layout. */
+int fft_batch_elements(const fft_batch* batch, int64_t* elements);
+
+/* Waits for the last execution and returns its status flags (0 = clean;
+ * bit 0 = a bounded dependency wait expired, results are not valid). */
+int fft_batch_status(fft_batch* batch, int* flags);
+
+/* Work items, persistent grid size and workspace bytes of the batch. */
+int fft_batch_info(const fft_batch* batch, int64_t* items, int64_t* grid, size_t* workspace_bytes);
+
+/* Waits for the batch's last execution, then frees it.  NULL-safe. */
+void fft_batch_destroy(fft_batch* batch);
+
+/*
+ * Serving slot: the device and pinned buffers for one in-flight launch of the
+ * uneven-batch kernel over the requests admitted in one scheduling step of a
+ * continuous-batching server (the same butterflies and tables as every other
+ * entry point).  Capacities: max_items work items, max_transforms
+ * single-unit transforms, max_large transforms of 2^14 points or more, and
+ * ws_bytes of workspace for them.  Returns NULL on error.
+ */
+fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int64_t max_items,
+                                      int64_t max_transforms, int max_large, size_t ws_bytes);
+
+/*
+ * Enqueues requests r < nreq on `stream`: batch[r] transforms of n[r] points
+ * (powers of two, 2 .. 2^18) each, transformed in place at element offsets
+ * off[r] + j * n[r] of the device buffer `data`.  First waits for the slot's
+ * previous launch.  FFT_ENOMEM if the step exceeds the slot's capacities.
+ */
+int fft_serve_slot_launch(fft_serve_slot* slot, const int64_t* n, const int64_t* batch,
+                          const int64_t* off, int64_t nreq, void* data, void* stream);
+
+/* 1 if the slot's last launch has finished (or none was made), 0 if running,
+ * negative on error. */
+int fft_serve_slot_query(fft_serve_slot* slot);
+
+/* Waits for the slot's last launch and returns its status flags (0 = clean). */
+int fft_serve_slot_status(fft_serve_slot* slot, int* flags);
+
+/* Waits for the slot's last launch, then frees it.  NULL-safe. */
+void fft_serve_slot_destroy(fft_serve_slot* slot);
 
 #ifdef __cplusplus
 }

@@ -54,6 +54,18 @@ _SIGS = {
     "fft_plan_set_workspace": ([_vp, _vp, _sz], _int),
     "fft_config_count": ([_i64, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
                           ctypes.POINTER(_int)], _int),
+    "fft_batch_create": ([_vp, _i64, _int, _int], _vp),
+    "fft_batch_create_tuned": ([_vp, _i64, _int, _int, _int, _int], _vp),
+    "fft_batch_execute": ([_vp, _vp, _vp, _vp], _int),
+    "fft_batch_elements": ([_vp, ctypes.POINTER(_i64)], _int),
+    "fft_batch_status": ([_vp, ctypes.POINTER(_int)], _int),
+    "fft_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
+    "fft_batch_destroy": ([_vp], None),
+    "fft_serve_slot_create": ([_int, _int, _i64, _i64, _int, _sz], _vp),
+    "fft_serve_slot_launch": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
+    "fft_serve_slot_query": ([_vp], _int),
+    "fft_serve_slot_status": ([_vp, ctypes.POINTER(_int)], _int),
+    "fft_serve_slot_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -150,6 +162,79 @@ def fft_config_count(n: int, dtype) -> tuple[int, int, int]:
     return a.value, b.value, c.value
 
 
+def fft_batch_create(sizes, dtype, kind, choice=None) -> int:
+    arr = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+    if choice is None:
+        h = _lib.fft_batch_create(arr.ctypes.data, arr.size, _dt(dtype), _kd(kind))
+    else:
+        h = _lib.fft_batch_create_tuned(arr.ctypes.data, arr.size, _dt(dtype), _kd(kind),
+                                        int(choice[0]), int(choice[1]))
+    if not h:
+        raise FFTError(FFT_EINVAL, fft_last_error())
+    return h
+
+
+def fft_batch_execute(batch: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _check(_lib.fft_batch_execute(batch, in_ptr, out_ptr, stream))
+
+
+def fft_batch_elements(batch: int) -> int:
+    v = _i64()
+    _check(_lib.fft_batch_elements(batch, ctypes.byref(v)))
+    return v.value
+
+
+def fft_batch_status(batch: int) -> int:
+    v = _int()
+    _check(_lib.fft_batch_status(batch, ctypes.byref(v)))
+    return v.value
+
+
+def fft_batch_info(batch: int) -> dict:
+    it, gr, ws = _i64(), _i64(), _sz()
+    _check(_lib.fft_batch_info(batch, ctypes.byref(it), ctypes.byref(gr), ctypes.byref(ws)))
+    return {"items": it.value, "grid": gr.value, "workspace_bytes": ws.value}
+
+
+def fft_batch_destroy(batch: int) -> None:
+    _lib.fft_batch_destroy(batch)
+
+
+def fft_serve_slot_create(dtype, kind, max_items: int, max_transforms: int, max_large: int,
+                          ws_bytes: int) -> int:
+    h = _lib.fft_serve_slot_create(_dt(dtype), _kd(kind), max_items, max_transforms, max_large,
+                                   ws_bytes)
+    if not h:
+        raise FFTError(FFT_ENOMEM, fft_last_error())
+    return h
+
+
+def fft_serve_slot_launch(slot: int, n, batch, off, data_ptr: int, stream: int = 0) -> None:
+    n = np.ascontiguousarray(n, dtype=np.int64)
+    batch = np.ascontiguousarray(batch, dtype=np.int64)
+    off = np.ascontiguousarray(off, dtype=np.int64)
+    assert n.size == batch.size == off.size
+    _check(_lib.fft_serve_slot_launch(slot, n.ctypes.data, batch.ctypes.data, off.ctypes.data,
+                                      n.size, data_ptr, stream))
+
+
+def fft_serve_slot_query(slot: int) -> bool:
+    rc = _lib.fft_serve_slot_query(slot)
+    if rc < 0:
+        raise FFTError(rc, fft_last_error())
+    return rc == 1
+
+
+def fft_serve_slot_status(slot: int) -> int:
+    v = _int()
+    _check(_lib.fft_serve_slot_status(slot, ctypes.byref(v)))
+    return v.value
+
+
+def fft_serve_slot_destroy(slot: int) -> None:
+    _lib.fft_serve_slot_destroy(slot)
+
+
 # ----------------------------------------------------------- torch marshalling
 
 def _torch_stream(stream) -> int:
@@ -197,6 +282,38 @@ class Plan:
     def close(self) -> None:
         if self.handle:
             fft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Owns an uneven-size batch; execute() takes packed torch tensors (total, 2)."""
+
+    def __init__(self, sizes, dtype="f16", kind="dual_select", choice=None):
+        self.sizes = np.asarray(sizes, dtype=np.int64)
+        self.dtype, self.kind = _dt(dtype), _kd(kind)
+        self.handle = fft_batch_create(self.sizes, self.dtype, self.kind, choice)
+        self.total = fft_batch_elements(self.handle)
+
+    def execute(self, x, y, stream=None) -> None:
+        _check_tensor(x, self.total, 1, self.dtype)
+        _check_tensor(y, self.total, 1, self.dtype)
+        fft_batch_execute(self.handle, x.data_ptr(), y.data_ptr(), _torch_stream(stream))
+
+    def status(self) -> int:
+        return fft_batch_status(self.handle)
+
+    def info(self) -> dict:
+        return fft_batch_info(self.handle)
+
+    def close(self) -> None:
+        if self.handle:
+            fft_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -1,0 +1,179 @@
+// Uneven-size batch: one persistent, work-queue kernel runs transforms of many
+// sizes in a single launch.  Work items are claimed in order with an atomic
+// counter; each item is one workgroup's worth of units of one size class and
+// runs the same register-pass / LDS-exchange code as the regular kernels.
+//
+// Transforms up to 2^13 points are single-unit items (whole transforms).
+// Larger ones (2^14 .. 2^18) use the two-kernel split of the global schedule
+// inside the same launch: column items (stages 1..log2 N1, into a workspace)
+// and row items (the remaining stages, into the output).  A row item waits on
+// a per-transform counter until all column items of its transform are done;
+// every column item is queued before every row item, so the items a row item
+// waits for have already been claimed by running workgroups and the wait ends.
+// The wait is bounded (spin_limit sleeps); on expiry the kernel records an
+// error flag and carries on, so every wave always reaches the end.
+#pragma once
+
+#include "batch_launch.hpp"
+#include "fft_device.hpp"
+
+namespace dsfft {
+
+constexpr int kBatchThreads = kHostBatchThreads;
+constexpr int kBatchMaxElems = 32;     // elements per lane, largest configuration
+
+// Work item (layout in batch_launch.hpp):
+//   cfg        configuration id (HostBatchCfg), one compiled unit configuration
+//   nunits     units in this item
+//   first      single-unit items: first index into the offset list;
+//              column/row items: first residue / row
+//   log_m      column/row items: log2(N / NU)
+//   wait_slot  row items: counter to wait on, else -1
+//   wait_need  row items: column items of the transform
+//   post_slot  column items: counter to increment when done, else -1
+//   in_off     column items: transform start in the input; row items: in the workspace
+//   out_off    column items: transform start in the workspace; row items: in the output
+using BatchItem = HostBatchItem;
+
+// Unit geometry of one work item.
+struct BatchGeo {
+    const int64_t* offs;
+    BatchItem it;
+    template <int LOG_NU, int MODE>
+    __device__ __forceinline__ UnitGeom get(int ul) const {
+        UnitGeom u;
+        u.in_stride = u.out_stride = 1;
+        u.q0 = 0;
+        u.log_lb = 0;
+        if (MODE == MODE_SMALL) {
+            const int64_t b = ul < it.nunits ? offs[it.first + ul] : 0;
+            u.base_in = u.base_out = b;
+        } else if (MODE == MODE_COLS) {
+            const int r0 = it.first + ul;
+            u.base_in = it.in_off + r0;
+            u.base_out = it.out_off + r0;
+            u.in_stride = u.out_stride = int64_t(1) << it.log_m;
+        } else {
+            const int q0 = it.first + ul;
+            u.q0 = q0;
+            u.log_lb = it.log_m;
+            u.base_in = it.in_off + ((int64_t)q0 << LOG_NU);
+            u.base_out = it.out_off + q0;
+            u.out_stride = int64_t(1) << it.log_m;
+        }
+        return u;
+    }
+    __device__ __forceinline__ bool active(int ul) const { return ul < it.nunits; }
+    __device__ __forceinline__ int64_t block_first(int) const { return 0; }
+    __device__ __forceinline__ int64_t block_units(int) const { return 0; }
+};
+
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
+__device__ __forceinline__ void batch_unit(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
+                                           const E* src, E* dst, const BatchGeo& geo) {
+    static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 256 threads");
+    static_assert((1 << LOG_E) <= kBatchMaxElems, "too many elements per lane");
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0>(v, lds, lt, src, dst, geo);
+}
+
+// Largest LDS footprint over the batch configurations, in elements.
+constexpr int batch_lds_elems() {
+    int m = 0;
+    const int sizes[] = {
+        256 * PassPlan<1, 1, 0, 0>::region(), 256 * PassPlan<2, 2, 0, 0>::region(),
+        256 * PassPlan<3, 3, 0, 0>::region(), 64 * PassPlan<4, 2, 2, 0>::region(),
+        64 * PassPlan<5, 3, 2, 0>::region(), 32 * PassPlan<6, 3, 3, 0>::region(),
+        32 * PassPlan<7, 4, 3, 0>::region(), 16 * PassPlan<8, 4, 4, 0>::region(),
+        16 * PassPlan<9, 5, 4, 0>::region(), 8 * PassPlan<10, 5, 5, 0>::region(),
+        4 * PassPlan<11, 5, 3, 3>::region(), 1 * PassPlan<12, 4, 4, 4>::region(),
+        1 * PassPlan<13, 5, 4, 4>::region(), 4 * PassPlan<10, 4, 3, 3>::region(),
+        2 * PassPlan<12, 5, 4, 3>::region(), 32 * PassPlan<7, 4, 3, 0>::region(),
+        16 * PassPlan<8, 4, 4, 0>::region(), 16 * PassPlan<9, 5, 4, 0>::region()};
+    for (int s : sizes) m = s > m ? s : m;
+    return m;
+}
+
+template <class E>
+__device__ __forceinline__ void batch_dispatch(int cfg, E* v, E* lds,
+                                               const typename TwOf<E>::type* __restrict__ lt,
+                                               const E* in, E* out, E* ws, const BatchGeo& g) {
+    switch (cfg) {
+        case HB_N2: batch_unit<E, 1, 1, 256, MODE_SMALL, 1, 0, 0>(v, lds, lt, in, out, g); break;
+        case HB_N4: batch_unit<E, 2, 2, 256, MODE_SMALL, 2, 0, 0>(v, lds, lt, in, out, g); break;
+        case HB_N8: batch_unit<E, 3, 3, 256, MODE_SMALL, 3, 0, 0>(v, lds, lt, in, out, g); break;
+        case HB_N16: batch_unit<E, 4, 2, 64, MODE_SMALL, 2, 2, 0>(v, lds, lt, in, out, g); break;
+        case HB_N32: batch_unit<E, 5, 3, 64, MODE_SMALL, 3, 2, 0>(v, lds, lt, in, out, g); break;
+        case HB_N64: batch_unit<E, 6, 3, 32, MODE_SMALL, 3, 3, 0>(v, lds, lt, in, out, g); break;
+        case HB_N128: batch_unit<E, 7, 4, 32, MODE_SMALL, 4, 3, 0>(v, lds, lt, in, out, g); break;
+        case HB_N256: batch_unit<E, 8, 4, 16, MODE_SMALL, 4, 4, 0>(v, lds, lt, in, out, g); break;
+        case HB_N512: batch_unit<E, 9, 5, 16, MODE_SMALL, 5, 4, 0>(v, lds, lt, in, out, g); break;
+        case HB_N1024: batch_unit<E, 10, 5, 8, MODE_SMALL, 5, 5, 0>(v, lds, lt, in, out, g); break;
+        case HB_N2048: batch_unit<E, 11, 5, 4, MODE_SMALL, 5, 3, 3>(v, lds, lt, in, out, g); break;
+        case HB_N4096: batch_unit<E, 12, 4, 1, MODE_SMALL, 4, 4, 4>(v, lds, lt, in, out, g); break;
+        case HB_N8192: batch_unit<E, 13, 5, 1, MODE_SMALL, 5, 4, 4>(v, lds, lt, in, out, g); break;
+        case HB_N1024_B: batch_unit<E, 10, 4, 4, MODE_SMALL, 4, 3, 3>(v, lds, lt, in, out, g); break;
+        case HB_N4096_B: batch_unit<E, 12, 5, 2, MODE_SMALL, 5, 4, 3>(v, lds, lt, in, out, g); break;
+        case HB_COLS128: batch_unit<E, 7, 4, 32, MODE_COLS, 4, 3, 0>(v, lds, lt, in, ws, g); break;
+        case HB_ROWS128: batch_unit<E, 7, 4, 32, MODE_ROWS, 4, 3, 0>(v, lds, lt, ws, out, g); break;
+        case HB_COLS256: batch_unit<E, 8, 4, 16, MODE_COLS, 4, 4, 0>(v, lds, lt, in, ws, g); break;
+        case HB_ROWS256: batch_unit<E, 8, 4, 16, MODE_ROWS, 4, 4, 0>(v, lds, lt, ws, out, g); break;
+        case HB_COLS512: batch_unit<E, 9, 5, 16, MODE_COLS, 5, 4, 0>(v, lds, lt, in, ws, g); break;
+        case HB_ROWS512: batch_unit<E, 9, 5, 16, MODE_ROWS, 5, 4, 0>(v, lds, lt, ws, out, g); break;
+        default: break;
+    }
+}
+
+// ctl[0]: queue head, ctl[1]: error flag, ctl[2 + s]: column items finished for
+// big transform s.  The control block is cleared by batch_reset_kernel before
+// each launch.
+template <class E>
+__global__ void __launch_bounds__(kBatchThreads)
+fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __restrict__ lt,
+                 const BatchItem* __restrict__ items, const int64_t* __restrict__ offs,
+                 int nitems, unsigned* ctl, int spin_limit) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    E* lds = reinterpret_cast<E*>(lds_raw);
+    __shared__ int s_item;
+    E v[kBatchMaxElems];
+    for (;;) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
+        __syncthreads();
+        const int idx = s_item;
+        __syncthreads();
+        if (idx >= nitems) break;
+        const BatchItem it = items[idx];
+        if (it.wait_slot >= 0) {
+            if (threadIdx.x == 0) {
+                int spins = 0;
+                while (__hip_atomic_load(&ctl[2 + it.wait_slot], __ATOMIC_ACQUIRE,
+                                         __HIP_MEMORY_SCOPE_AGENT) < (unsigned)it.wait_need) {
+                    if (++spins > spin_limit) {
+                        atomicOr(&ctl[1], 1u);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(8);
+                }
+            }
+            __syncthreads();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        const BatchGeo geo{offs, it};
+        batch_dispatch<E>(it.cfg, v, lds, lt, in, out, ws, geo);
+        if (it.post_slot >= 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            __syncthreads();
+            if (threadIdx.x == 0)
+                __hip_atomic_fetch_add(&ctl[2 + it.post_slot], 1u, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();   // the item's LDS is consumed before the next item reuses it
+    }
+}
+
+// Clears the control block (a kernel rather than a memset node, so the graph
+// holds kernels only).
+__global__ void batch_reset_kernel(unsigned* ctl, int n) {
+    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) ctl[i] = 0u;
+}
+
+}  // namespace dsfft

@@ -230,13 +230,30 @@ __device__ __forceinline__ void stage_out(const E* lds, E* out, int64_t first, i
     }
 }
 
+// Where the units of one workgroup live: a regular launch takes UPW
+// consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
+// units of one work item (BatchGeo, in fft_batch.hpp).
+struct GridGeo {
+    int64_t ublk, units;
+    int log_m;
+    template <int LOG_NU, int MODE>
+    __device__ __forceinline__ UnitGeom get(int ul) const {
+        return unit_geom<LOG_NU, MODE>(ublk + ul, log_m);
+    }
+    __device__ __forceinline__ bool active(int ul) const { return ublk + ul < units; }
+    // staging: the workgroup's units are elements [first, first + count)
+    __device__ __forceinline__ int64_t block_first(int log_nu) const { return ublk << log_nu; }
+    __device__ __forceinline__ int64_t block_units(int upw) const {
+        return units - ublk < upw ? units - ublk : upw;
+    }
+};
+
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
 // LR radix-2 stages per group, scatter (LDS or global).
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int P>
+          int P, class Geo>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
-                                          const E* in, E* out, int64_t ublk, int64_t units,
-                                          int log_m) {
+                                          const E* in, E* out, const Geo& gp) {
     using TW = typename TwOf<E>::type;
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2>;
     constexpr int NP = PP::NP;
@@ -256,18 +273,17 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         const int tid = threadIdx.x;
         const int ul = unit_fast ? (tid % UPW) : (tid / G);
         const int g = unit_fast ? (tid / UPW) : (tid % G);
-        const int64_t unit = ublk + ul;
-        const bool active = unit < units;
+        const bool active = gp.active(ul);
         E* reg = lds + ul * RS;
-        const UnitGeom geo = unit_geom<LOG_NU, MODE>(unit, log_m);
+        const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul);
 
         // ---- gather
         if constexpr (P == 0 && STG) {
             // The workgroup's units are contiguous in memory: copy the block
             // into LDS (natural order) with 16-byte streaming loads, then
             // gather the pass's decimated groups from LDS.
-            stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, ublk << LOG_NU,
-                                              (units - ublk < UPW ? units - ublk : UPW) << LOG_NU);
+            stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, gp.block_first(LOG_NU),
+                                              gp.block_units(UPW) << LOG_NU);
             const E* nat = lds + ul * NU;
 #pragma unroll
             for (int u = 0; u < GPL; ++u) {
@@ -347,8 +363,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 for (int e = 0; e < R; ++e) nat[q + L0 * e] = v[u * R + e];
             }
             __syncthreads();
-            stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, ublk << LOG_NU,
-                                               (units - ublk < UPW ? units - ublk : UPW) << LOG_NU);
+            stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
+                                               gp.block_units(UPW) << LOG_NU);
         } else {
             if (active) {
 #pragma unroll
@@ -362,8 +378,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 }
             }
         }
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, P + 1>(v, lds, lt, in, out,
-                                                                          ublk, units, log_m);
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, P + 1>(v, lds, lt, in, out, gp);
     }
 }
 
@@ -382,9 +397,8 @@ fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ 
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     E v[1 << LOG_E];
-    const int64_t ublk = (int64_t)blockIdx.x * UPW;
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, 0>(v, lds, lt, in, out, ublk,
-                                                                  units, log_m);
+    const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m};
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, 0>(v, lds, lt, in, out, gp);
 }
 
 }  // namespace dsfft

@@ -1,0 +1,172 @@
+// Serving slots: one in-flight launch of the persistent batch kernel over the
+// requests admitted in one scheduling step.  The work list is built on the
+// host, staged through pinned memory and copied to the slot's device buffers
+// on the slot's stream, so consecutive steps on different slots overlap on
+// the device.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <memory>
+#include <vector>
+
+#include "batch_launch.hpp"
+#include "dsfft.h"
+#include "plan.hpp"
+#include "tables.hpp"
+
+struct fft_serve_slot {
+    int dtype = 0, kind = 0, device = 0;
+    std::shared_ptr<dsfft::DeviceTable> table;
+    dsfft::HostBatchItem* d_items = nullptr;
+    int64_t* d_offs = nullptr;
+    unsigned* d_ctl = nullptr;
+    void* ws = nullptr;
+    dsfft::HostBatchItem* h_items = nullptr;   // pinned staging
+    int64_t* h_offs = nullptr;
+    int64_t item_cap = 0, offs_cap = 0;
+    int slot_cap = 0;
+    size_t ws_cap = 0;
+    int resident = 1;
+    int cfg_choice[17] = {};
+    hipEvent_t done = nullptr;
+    bool launched = false;
+    std::vector<int64_t> tn, toff, offs;
+    std::vector<dsfft::HostBatchItem> items;
+    ~fft_serve_slot();
+};
+
+fft_serve_slot::~fft_serve_slot() {
+    if (done) {
+        if (launched) (void)hipEventSynchronize(done);
+        (void)hipEventDestroy(done);
+    }
+    if (d_items) (void)hipFree(d_items);
+    if (d_offs) (void)hipFree(d_offs);
+    if (d_ctl) (void)hipFree(d_ctl);
+    if (ws) (void)hipFree(ws);
+    if (h_items) (void)hipHostFree(h_items);
+    if (h_offs) (void)hipHostFree(h_offs);
+}
+
+using namespace dsfft;
+
+extern "C" {
+
+fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int64_t max_items,
+                                      int64_t max_transforms, int max_large, size_t ws_bytes) {
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32) {
+        set_error(FFT_EINVAL, "dtype must be FFT_F16 or FFT_F32");
+        return nullptr;
+    }
+    if ((int)kind < 0 || (int)kind > 3 || max_items < 1 || max_transforms < 1 || max_large < 0) {
+        set_error(FFT_EINVAL, "bad serving slot parameters");
+        return nullptr;
+    }
+    std::unique_ptr<fft_serve_slot> s(new fft_serve_slot());
+    s->dtype = (int)dtype;
+    s->kind = (int)kind;
+    s->item_cap = max_items;
+    s->offs_cap = max_transforms;
+    s->slot_cap = max_large;
+    s->ws_cap = ws_bytes;
+    for (int m = 1; m <= 13; ++m) s->cfg_choice[m] = kSmallCfg[m];
+    hipError_t e = hipGetDevice(&s->device);
+    if (e != hipSuccess) { hip_error(e, "hipGetDevice"); return nullptr; }
+    if (get_table(int64_t(1) << 18, s->dtype, s->kind, &s->table) != FFT_OK) return nullptr;
+    if ((e = hipMalloc(&s->d_items, sizeof(HostBatchItem) * max_items)) != hipSuccess ||
+        (e = hipMalloc(&s->d_offs, sizeof(int64_t) * max_transforms)) != hipSuccess ||
+        (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * (2 + max_large))) != hipSuccess ||
+        (ws_bytes && (e = hipMalloc(&s->ws, ws_bytes)) != hipSuccess) ||
+        (e = hipHostMalloc((void**)&s->h_items, sizeof(HostBatchItem) * max_items, 0)) != hipSuccess ||
+        (e = hipHostMalloc((void**)&s->h_offs, sizeof(int64_t) * max_transforms, 0)) != hipSuccess) {
+        set_error(e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP, "serving slot allocation failed");
+        return nullptr;
+    }
+    if (batch_resident_grid(s->dtype, s->device, &s->resident) != FFT_OK) return nullptr;
+    if ((e = hipEventCreateWithFlags(&s->done, hipEventDisableTiming)) != hipSuccess) {
+        hip_error(e, "hipEventCreate");
+        return nullptr;
+    }
+    return s.release();
+}
+
+// Launches requests r = 0..nreq-1: batch[r] transforms of n[r] points each,
+// in place at element offsets off[r] + j * n[r] of `data`.  Waits first for
+// the slot's previous launch (its staging buffers are reused).
+int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* batch,
+                          const int64_t* off, int64_t nreq, void* data, void* stream) {
+    if (!s || !n || !batch || !off || nreq < 0) return set_error(FFT_EINVAL, "null argument");
+    if (!data) return set_error(FFT_EINVAL, "null data pointer");
+    if ((uintptr_t)data % (uintptr_t)elem_bytes(s->dtype))
+        return set_error(FFT_EINVAL, "data must be aligned to the element size");
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e;
+    if (s->launched && (e = hipEventSynchronize(s->done)) != hipSuccess)
+        return hip_error(e, "hipEventSynchronize");
+    s->tn.clear();
+    s->toff.clear();
+    for (int64_t r = 0; r < nreq; ++r) {
+        const int64_t v = n[r];
+        if (v < 2 || (v & (v - 1)) || v > (int64_t(1) << 18) || batch[r] < 1 || off[r] < 0)
+            return set_error(FFT_EINVAL, "request sizes must be powers of two in [2, 2^18]");
+        for (int64_t j = 0; j < batch[r]; ++j) {
+            s->tn.push_back(v);
+            s->toff.push_back(off[r] + j * v);
+        }
+    }
+    int64_t ws_elems = 0;
+    int nslots = 0;
+    build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice, s->items, s->offs,
+               ws_elems, nslots);
+    if ((int64_t)s->items.size() > s->item_cap || (int64_t)s->offs.size() > s->offs_cap ||
+        nslots > s->slot_cap || (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
+        return set_error(FFT_ENOMEM, "step exceeds the slot's capacity");
+    if (s->items.empty()) return FFT_OK;
+    std::copy(s->items.begin(), s->items.end(), s->h_items);
+    std::copy(s->offs.begin(), s->offs.end(), s->h_offs);
+    if ((e = hipMemcpyAsync(s->d_items, s->h_items, sizeof(HostBatchItem) * s->items.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_error(e, "hipMemcpyAsync(items)");
+    if (!s->offs.empty() &&
+        (e = hipMemcpyAsync(s->d_offs, s->h_offs, sizeof(int64_t) * s->offs.size(),
+                            hipMemcpyHostToDevice, st)) != hipSuccess)
+        return hip_error(e, "hipMemcpyAsync(offsets)");
+    if ((e = launch_batch_reset(s->d_ctl, 2 + nslots, st)) != hipSuccess)
+        return hip_error(e, "launch(reset)");
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->items.size(), s->resident));
+    if ((e = launch_batch(s->dtype, data, data, s->ws, s->table->ptr, s->d_items, s->d_offs,
+                          (int)s->items.size(), s->d_ctl, kSpinLimit, grid, st)) != hipSuccess)
+        return hip_error(e, "launch(batch)");
+    if ((e = hipEventRecord(s->done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
+    s->launched = true;
+    return FFT_OK;
+}
+
+// 1 if the slot's last launch has finished (or none was made), 0 if running.
+int fft_serve_slot_query(fft_serve_slot* s) {
+    if (!s) return set_error(FFT_EINVAL, "null slot");
+    if (!s->launched) return 1;
+    hipError_t e = hipEventQuery(s->done);
+    if (e == hipSuccess) return 1;
+    if (e == hipErrorNotReady) return 0;
+    return hip_error(e, "hipEventQuery");
+}
+
+// Status flags of the slot's last launch after waiting for it (bit 0: a
+// bounded dependency wait expired).
+int fft_serve_slot_status(fft_serve_slot* s, int* flags) {
+    if (!s || !flags) return set_error(FFT_EINVAL, "null argument");
+    *flags = 0;
+    if (!s->launched) return FFT_OK;
+    hipError_t e = hipEventSynchronize(s->done);
+    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
+    unsigned f = 0;
+    if ((e = hipMemcpy(&f, s->d_ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_error(e, "hipMemcpy(status)");
+    *flags = (int)f;
+    return FFT_OK;
+}
+
+void fft_serve_slot_destroy(fft_serve_slot* s) { delete s; }
+
+}  // extern "C"
