@@ -1,0 +1,68 @@
+"""GPU tests of the continuous-batching serving loop: every checked request's
+result is the same alone (a regular plan on the same input) as in the mix,
+steps batch several requests and overlap on the device, and admission keeps
+in-flight bytes under the budget."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2604_00567_amd import binding, inputs
+from paper_2604_00567_amd.serve import Server, run_per_request
+from tests.gpu_util import mismatches
+
+pytestmark = pytest.mark.gpu
+
+
+def small_trace(k, seed, rate=200000.0, log_hi=14):
+    tr = inputs.poisson_trace(rate, k / rate, seed, log_lo=8, log_hi=log_hi, batch_hi=8)
+    return tr
+
+
+def test_results_alone_equal_results_in_mix():
+    import torch
+    tr = small_trace(400, 21, log_hi=16)
+    srv = Server(slots=3, slot_bytes=256 << 20, keep_io=True, seed=5)
+    try:
+        stats = srv.run(tr, max_step_requests=32)
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    assert stats["requests"] == tr["t"].size
+    assert stats["mean_requests_per_step"] > 1.0           # steps batch requests
+    assert stats["max_concurrent_steps"] >= 2               # steps overlap on the device
+    rng = np.random.default_rng(0)
+    pick = rng.choice(tr["t"].size, 40, replace=False)
+    for rid in pick:
+        n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+        x = srv.inputs[rid].reshape(b, n, 2)
+        y_mix = srv.outputs[rid].reshape(b, n, 2)
+        y_alone = torch.empty_like(x)
+        p = binding.Plan(n, b, dt, "dual_select")
+        p.execute(x, y_alone)
+        torch.cuda.synchronize()
+        p.close()
+        assert mismatches(y_mix.cpu().numpy(), y_alone.cpu().numpy()) == 0, (rid, n, b, dt)
+    # and a few against the oracle's emulation
+    for rid in pick[:6]:
+        n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+        x = srv.inputs[rid].reshape(b, n, 2).cpu().numpy()
+        y = srv.outputs[rid].reshape(b, n, 2).cpu().numpy()
+        assert mismatches(y, oracle.emulate(x, "dual_select", dt)) == 0
+
+
+def test_budget_is_respected():
+    tr = small_trace(300, 22)
+    budget = 48 << 20
+    srv = Server(slots=4, budget_bytes=budget, slot_bytes=64 << 20, seed=6)
+    try:
+        stats = srv.run(tr)
+    finally:
+        srv.close()
+    assert stats["requests"] == tr["t"].size
+    assert 0 < stats["max_inflight_bytes"] <= budget
+
+
+def test_per_request_baseline_runs():
+    tr = small_trace(200, 23, rate=20000.0)
+    stats = run_per_request(tr, streams=2)
+    assert stats["requests"] == tr["t"].size and stats["p99_ms"] >= stats["p50_ms"] > 0
