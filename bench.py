@@ -1,14 +1,20 @@
 """Benchmark: batched FP16 FFT throughput (GB/s, % of HBM peak) of the
 dual-select six-FMA path on one MI355X, at stated error against FP64.
 
-Workload (one step = one fft_execute over the whole batch, inputs resident in
-HBM): N = 1024, batch = 65536, binary16 interleaved complex, re/im uniform
-[-1, 1) from a fixed seed, dual-select table.  The N = 4096 x 16384 case is
-timed the same way and reported alongside.  Buffer sets rotate over more than
-1 GB so the 256 MB memory-side cache cannot serve repeated inputs.
+Headline step (timed K times, inputs resident in HBM): one fft_execute over
+N = 1024 x 65536 transforms, binary16 interleaved complex, re/im uniform
+[-1, 1) (seed 2), dual-select table.  Buffer sets rotate over more than 1 GB
+so the 256 MB memory-side cache cannot serve repeated inputs.  Algorithmic
+bytes per transform: 2 * N * 4 (one read, one write of binary16 pairs); the
+twiddle table is excluded.
 
-Prints one JSON line.  Algorithmic bytes per transform: 2 * N * 4 (one read,
-one write of binary16 pairs); the twiddle table is excluded.
+Reported beside it (not the headline value): N = 4096 x 16384; the large-N
+sweep N = 2^10..2^20 with batch * N = 2^26 (binary16 and binary32); the
+binary32 single-size case N = 1024 x 16 with all table kinds; the uneven
+batch of 4096 transforms with N = 2^U, U uniform over 6..16, in one graph
+replay of the persistent kernel, against one plan per size class; the serving
+loop on Poisson arrivals at 20k requests/s against one launch per request;
+and the CPU oracle on the host cores.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -24,73 +30,178 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+EB = {"f16": 4, "f32": 8}
 
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def time_case(torch, binding, inputs, n, batch, dtype, kind, steps, warmup, seed):
-    """Returns timing dict for one (n, batch) case, with rotating buffer sets."""
-    eb = 4 if dtype == "f16" else 8
-    set_bytes = 2 * n * batch * eb
-    nsets = max(2, int(np.ceil(1.2e9 / set_bytes)))
-    x0 = inputs.uniform(n, batch, seed=seed, dtype=dtype)
-    xs, ys = [], []
+def rotating_sets(torch, x0: np.ndarray, min_bytes: float = 1.2e9):
     first = torch.from_numpy(x0).to("cuda:0")
-    for s in range(nsets):
-        xs.append(first if s == 0 else first.clone())
-        ys.append(torch.empty_like(first))
-    plan = binding.Plan(n, batch, dtype, kind)
-    stream = torch.cuda.current_stream()
+    per = 2 * first.numel() * first.element_size()
+    nsets = max(2, int(np.ceil(min_bytes / per)))
+    xs = [first] + [first.clone() for _ in range(nsets - 1)]
+    ys = [torch.empty_like(first) for _ in range(nsets)]
+    return xs, ys
+
+
+def timed_loop(torch, run, nsets: int, steps: int, warmup: int):
+    """Times `steps` calls of run(i) between one pair of HIP events on the
+    current stream (the stream the library launches on), after `warmup`
+    untimed calls; wall time is taken between device synchronisations."""
     for i in range(warmup):
-        plan.execute(xs[i % nsets], ys[i % nsets])
+        run(i % nsets)
     torch.cuda.synchronize()
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
-    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    a.record()
     for i in range(steps):
-        starts[i].record(stream)
-        plan.execute(xs[i % nsets], ys[i % nsets])
-        ends[i].record(stream)
+        run(i % nsets)
+    b.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    kern_ms = [a.elapsed_time(b) for a, b in zip(starts, ends)]
-    info = plan.info()
-    out = ys[(steps - 1) % nsets]
-    xin = xs[(steps - 1) % nsets]
-    algo_bytes = 2.0 * n * batch * eb
-    res = {
-        "n": n, "batch": batch, "dtype": dtype, "kind": kind,
-        "wall_ms_per_step": wall * 1e3 / steps,
-        "kernel_ms_mean": float(np.mean(kern_ms)),
-        "kernel_ms_median": float(np.median(kern_ms)),
-        "kernel_ms_min": float(np.min(kern_ms)),
-        "algo_bytes_per_launch": algo_bytes,
-        "config": info["config"],
-        "buffer_sets": nsets,
-    }
-    res["gbs"] = algo_bytes / (res["wall_ms_per_step"] * 1e-3) / 1e9
-    res["gbs_kernel"] = algo_bytes / (res["kernel_ms_mean"] * 1e-3) / 1e9
-    res["transforms_per_s"] = batch / (res["wall_ms_per_step"] * 1e-3)
+    return wall / steps, a.elapsed_time(b) / 1e3 / steps
+
+
+def time_plan(torch, binding, inputs, n, batch, dtype, kind, steps, warmup, seed, gen="uniform",
+              distinct=None):
+    """Times a plan on rotating buffer sets.  With `distinct`, only that many
+    transforms are generated and tiled to the batch on the device (the data
+    values do not change the timing; the error sample uses the generated ones)."""
+    x0 = getattr(inputs, gen)(n, min(batch, distinct or batch), seed=seed, dtype=dtype)
+    if x0.shape[0] < batch:
+        reps = batch // x0.shape[0]
+        big = torch.from_numpy(x0).to("cuda:0").repeat(reps, 1, 1).cpu().numpy()
+        xs, ys = rotating_sets(torch, big)
+        del big
+    else:
+        xs, ys = rotating_sets(torch, x0)
+    plan = binding.Plan(n, batch, dtype, kind)
+    wall, dev = timed_loop(torch, lambda i: plan.execute(xs[i], ys[i]), len(xs), steps, warmup)
+    algo = 2.0 * n * batch * EB[dtype]
+    res = {"n": n, "batch": batch, "dtype": dtype, "kind": kind,
+           "ms_per_step": wall * 1e3, "kernel_ms": dev * 1e3,
+           "gbs": algo / wall / 1e9, "gbs_kernel": algo / dev / 1e9,
+           "transforms_per_s": batch / wall, "algo_bytes": algo,
+           "config": plan.info()["config"], "buffer_sets": len(xs)}
+    last = ys[(steps - 1) % len(xs)]
     plan.close()
-    return res, xin, out, x0
+    return res, x0, last
 
 
 def error_vs_fp64(x: np.ndarray, y: np.ndarray):
-    """rel-L2 / max-abs of y against an FP64 FFT (numpy, complex128) of the same
+    """rel-L2 / max-abs of y against an FP64 FFT (numpy complex128) of the same
     quantised inputs."""
     xc = x[..., 0].astype(np.float64) + 1j * x[..., 1].astype(np.float64)
     ref = np.fft.fft(xc, axis=-1)
     yc = y[..., 0].astype(np.float64) + 1j * y[..., 1].astype(np.float64)
-    finite = np.isfinite(yc)
-    nonfinite = int(np.count_nonzero(~finite))
+    nonfinite = int(np.count_nonzero(~np.isfinite(yc)))
     if nonfinite:
         return {"rel_l2": None, "max_abs": None, "nonfinite": nonfinite}
     d = np.abs(yc - ref)
     return {"rel_l2": float(np.linalg.norm(d) / np.linalg.norm(ref)), "max_abs": float(d.max()),
             "nonfinite": 0}
+
+
+def run_once(torch, binding, x: np.ndarray, dtype: str, kind: str) -> np.ndarray:
+    xt = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    yt = torch.empty_like(xt)
+    p = binding.Plan(x.shape[1], x.shape[0], dtype, kind)
+    p.execute(xt, yt)
+    torch.cuda.synchronize()
+    p.close()
+    return yt.cpu().numpy()
+
+
+def bench_uneven(torch, binding, inputs, steps, warmup):
+    sizes = inputs.uneven_sizes(4096, seed=4)
+    x0 = inputs.packed_uniform(sizes, 4, "f16")
+    xs, ys = rotating_sets(torch, x0, min_bytes=0.8e9)
+    b = binding.Batch(sizes, "f16", "dual_select")
+    wall, dev = timed_loop(torch, lambda i: b.execute(xs[i], ys[i]), len(xs), steps, warmup)
+    assert b.status() == 0
+    info = b.info()
+    b.close()
+    algo = 2.0 * float(np.sum(sizes)) * 4
+    # baseline: one regular plan per size class on the same data
+    plans, views = [], []
+    order = np.argsort(sizes, kind="stable")
+    for m in range(6, 17):
+        idx = np.flatnonzero(sizes == (1 << m))
+        if idx.size:
+            plans.append(binding.Plan(1 << m, int(idx.size), "f16", "dual_select"))
+            views.append(int(idx.size) * (1 << m))
+    xg = torch.from_numpy(np.ascontiguousarray(
+        np.concatenate([x0[int(np.sum(sizes[:i])):int(np.sum(sizes[:i])) + int(sizes[i])]
+                        for i in order]))).to("cuda:0")
+    yg = torch.empty_like(xg)
+
+    def per_class(_):
+        o = 0
+        for p, cnt in zip(plans, views):
+            p.execute(xg[o:o + cnt], yg[o:o + cnt])
+            o += cnt
+
+    wall_c, _ = timed_loop(torch, per_class, 1, steps, warmup)
+    for p in plans:
+        p.close()
+    return {"transforms": 4096, "elements": int(np.sum(sizes)), "ms_per_step": wall * 1e3,
+            "gbs": algo / wall / 1e9, "gbs_kernel": algo / dev / 1e9,
+            "pct_hbm_peak": 100 * algo / wall / 1e9 / HBM_PEAK_GBS,
+            "items": info["items"], "grid": info["grid"],
+            "per_class_plans_gbs": algo / wall_c / 1e9, "per_class_launches": len(plans),
+            "form": "one HIP-graph replay of the persistent kernel per step"}
+
+
+def bench_sweep(torch, binding, inputs, steps):
+    out = []
+    for dt in ("f16", "f32"):
+        for m in range(10, 21):
+            n = 1 << m
+            batch = (1 << 26) >> m
+            r, x0, y = time_plan(torch, binding, inputs, n, batch, dt, "dual_select", steps, 2,
+                                 seed=300 + m, gen="tones", distinct=max(1, (1 << 20) >> m))
+            k = min(batch, 4, x0.shape[0])
+            e = error_vs_fp64(x0[:k], y[:k].cpu().numpy())
+            out.append({"n": n, "batch": batch, "dtype": dt, "gbs": round(r["gbs"], 1),
+                        "pct_hbm_peak": round(100 * r["gbs"] / HBM_PEAK_GBS, 2),
+                        "rel_l2": e["rel_l2"], "config": r["config"]})
+            del x0, y
+            torch.cuda.empty_cache()
+    return out
+
+
+def bench_single_fp32(torch, binding, inputs):
+    n, batch = 1024, 16
+    x = inputs.normal(n, batch, 1, "f32")
+    out = {}
+    for kind in ("dual_select", "linzer_feig", "cosine"):
+        xt = torch.from_numpy(x).to("cuda:0")
+        yt = torch.empty_like(xt)
+        p = binding.Plan(n, batch, "f32", kind)
+        wall, dev = timed_loop(torch, lambda i: p.execute(xt, yt), 1, 200, 10)
+        p.close()
+        out[kind] = {"us_per_execute": wall * 1e6, "kernel_us": dev * 1e6,
+                     **error_vs_fp64(x, yt.cpu().numpy())}
+    return out
+
+
+def bench_serving(torch, seconds: float, seed: int = 9):
+    from paper_2604_00567_amd import inputs
+    from paper_2604_00567_amd.serve import Server, run_per_request
+    tr = inputs.poisson_trace(20000.0, seconds, seed)
+    srv = Server(slots=4, budget_bytes=64 << 30, slot_bytes=1 << 30, seed=seed)
+    try:
+        cont = srv.run(tr)
+    finally:
+        srv.close()
+    torch.cuda.empty_cache()
+    base = run_per_request(tr, streams=4, seed=seed)
+    return {"trace": f"Poisson 20000 req/s for {seconds:g} s ({tr['t'].size} requests), "
+                     "N=2^8..2^18, batch 1..64, 75% f16 / 25% f32, N(0,1) generated on the GPU",
+            "continuous": cont, "one_launch_per_request": base}
 
 
 def cpu_baseline(x0: np.ndarray, n: int, target_s: float = 10.0):
@@ -121,6 +232,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="time only the headline step (used for profiling)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -133,33 +247,12 @@ def main():
     from paper_2604_00567_amd import binding, inputs
 
     log("timing N=1024 x 65536 f16 dual-select")
-    main_res, xin, yout, x0 = time_case(torch, binding, inputs, 1024, 65536, "f16",
-                                        "dual_select", args.steps, args.warmup, seed=2)
-    log(f"N=1024: {main_res['gbs']:.0f} GB/s wall, {main_res['gbs_kernel']:.0f} GB/s kernel")
+    main_res, x0, yout = time_plan(torch, binding, inputs, 1024, 65536, "f16", "dual_select",
+                                   args.steps, args.warmup, seed=2)
+    log(f"N=1024: {main_res['gbs']:.0f} GB/s wall, {main_res['gbs_kernel']:.0f} GB/s device")
     pick = np.random.default_rng(3).choice(65536, 256, replace=False)
-    y_host = yout.cpu().numpy()
-    err = error_vs_fp64(x0[pick], y_host[pick])
-    bound = (1 + 2.0 ** -11) ** 10 - 1
-
-    # the comparison tables on the same sampled transforms
-    lf = {}
-    for kind in ("linzer_feig", "lf_w0_exempt", "cosine"):
-        xs = torch.from_numpy(np.ascontiguousarray(x0[pick])).to("cuda:0")
-        ys = torch.empty_like(xs)
-        p = binding.Plan(1024, len(pick), "f16", kind)
-        p.execute(xs, ys)
-        torch.cuda.synchronize()
-        p.close()
-        lf[kind] = error_vs_fp64(x0[pick], ys.cpu().numpy())
-
-    log("timing N=4096 x 16384 f16 dual-select")
-    sec, _, yout2, x02 = time_case(torch, binding, inputs, 4096, 16384, "f16", "dual_select",
-                                   args.steps, args.warmup, seed=4)
-    pick2 = np.random.default_rng(5).choice(16384, 64, replace=False)
-    err2 = error_vs_fp64(x02[pick2], yout2.cpu().numpy()[pick2])
-    log(f"N=4096: {sec['gbs']:.0f} GB/s wall, {sec['gbs_kernel']:.0f} GB/s kernel")
-
-    ms = main_res["wall_ms_per_step"]
+    err = error_vs_fp64(x0[pick], yout.cpu().numpy()[pick])
+    ms = main_res["ms_per_step"]
     result = {
         "metric": "batched FP16 FFT GB/s (% HBM peak) at stated err vs FP64",
         "value": round(main_res["gbs"], 1),
@@ -182,18 +275,44 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(main_res["gbs_kernel"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(main_res["gbs_kernel"] / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel_ms_mean": round(main_res["kernel_ms_mean"], 4),
-                     "algo_bytes_per_launch": main_res["algo_bytes_per_launch"]},
-        "error_vs_fp64": dict(err, bound=bound, sample_transforms=len(pick)),
-        "comparison_tables": lf,
-        "n4096": {"value": round(sec["gbs"], 1), "unit": "GB/s",
-                  "pct_hbm_peak": round(100 * sec["gbs"] / HBM_PEAK_GBS, 2),
-                  "kernel_gbs": round(sec["gbs_kernel"], 1),
-                  "ms_per_step": round(sec["wall_ms_per_step"], 4),
-                  "transforms_per_s": round(sec["transforms_per_s"]),
-                  "kernel": sec["config"],
-                  "error_vs_fp64": dict(err2, bound=(1 + 2.0 ** -11) ** 12 - 1)},
+                     "kernel_ms_mean": round(main_res["kernel_ms"], 4),
+                     "algo_bytes_per_launch": main_res["algo_bytes"]},
+        "error_vs_fp64": dict(err, bound=(1 + 2.0 ** -11) ** 10 - 1, sample_transforms=len(pick)),
     }
+    if not args.no_extras:
+        lf = {}
+        for kind in ("linzer_feig", "lf_w0_exempt", "cosine"):
+            lf[kind] = error_vs_fp64(x0[pick], run_once(torch, binding, x0[pick], "f16", kind))
+        ds_max = err["max_abs"]
+        lf["dual_select_vs_lf_w0_exempt_max_abs_ratio"] = (
+            lf["lf_w0_exempt"]["max_abs"] / ds_max if ds_max else None)
+        result["comparison_tables"] = lf
+        del yout
+        log("timing N=4096 x 16384 f16 dual-select")
+        sec, x02, y2 = time_plan(torch, binding, inputs, 4096, 16384, "f16", "dual_select",
+                                 args.steps, args.warmup, seed=4)
+        p2 = np.random.default_rng(5).choice(16384, 64, replace=False)
+        result["n4096"] = {"value": round(sec["gbs"], 1), "unit": "GB/s",
+                           "pct_hbm_peak": round(100 * sec["gbs"] / HBM_PEAK_GBS, 2),
+                           "device_gbs": round(sec["gbs_kernel"], 1),
+                           "ms_per_step": round(sec["ms_per_step"], 4),
+                           "transforms_per_s": round(sec["transforms_per_s"]),
+                           "kernel": sec["config"],
+                           "error_vs_fp64": dict(error_vs_fp64(x02[p2], y2.cpu().numpy()[p2]),
+                                                 bound=(1 + 2.0 ** -11) ** 12 - 1)}
+        del x02, y2
+        torch.cuda.empty_cache()
+        log("uneven batch (4096 transforms, 2^6..2^16)")
+        result["uneven_batch"] = bench_uneven(torch, binding, inputs, 20, 3)
+        torch.cuda.empty_cache()
+        log("large-N sweep")
+        result["sweep"] = bench_sweep(torch, binding, inputs, 10)
+        log("binary32 N=1024 x 16, three tables")
+        result["single_fp32"] = bench_single_fp32(torch, binding, inputs)
+        torch.cuda.empty_cache()
+        if args.serve_seconds > 0:
+            log(f"serving, {args.serve_seconds:g} s of trace")
+            result["serving"] = bench_serving(torch, args.serve_seconds)
     if not args.no_cpu:
         log("cpu baseline (oracle emulation)")
         result["cpu_baseline"] = cpu_baseline(x0, 1024, args.cpu_seconds)

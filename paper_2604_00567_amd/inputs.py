@@ -54,14 +54,25 @@ def tone_prescale(n: int, dtype: str) -> float:
 def tones(n: int, batch: int, seed: int, dtype: str = "f16", ntones: int = 8,
           noise_sigma: float = 0.01) -> np.ndarray:
     rng = np.random.default_rng(seed)
-    idx = np.arange(n, dtype=np.float64)
+    k = min(ntones, n)
+    # k distinct integer frequencies per transform (rows with a repeat are redrawn)
+    f = rng.integers(0, n, (batch, k))
+    while True:
+        srt = np.sort(f, axis=1)
+        bad = np.flatnonzero(np.any(srt[:, 1:] == srt[:, :-1], axis=1)) if k > 1 else []
+        if len(bad) == 0:
+            break
+        f[bad] = rng.integers(0, n, (len(bad), k))
     out = np.empty((batch, n, 2), np.float64)
-    for b in range(batch):
-        f = rng.choice(n, size=min(ntones, n), replace=False).astype(np.float64)
-        # exp(+j 2 pi f n / N) with the product f*n reduced mod N exactly (integers)
-        ph = 2.0 * np.pi * (np.outer(f, idx) % n) / n
-        out[b, :, 0] = np.cos(ph).sum(axis=0)
-        out[b, :, 1] = np.sin(ph).sum(axis=0)
+    rows = max(1, (1 << 22) // n)
+    for b0 in range(0, batch, rows):
+        fb = f[b0:b0 + rows]
+        # sum_f exp(+j 2 pi f t / N), synthesised as N * ifft of unit spikes at f
+        spec = np.zeros((fb.shape[0], n), np.complex128)
+        np.put_along_axis(spec, fb, 1.0, axis=1)
+        sig = np.fft.ifft(spec, axis=1) * n
+        out[b0:b0 + rows, :, 0] = sig.real
+        out[b0:b0 + rows, :, 1] = sig.imag
     out += rng.normal(0.0, noise_sigma, out.shape)
     out *= tone_prescale(n, dtype)
     return _round(out, dtype)
