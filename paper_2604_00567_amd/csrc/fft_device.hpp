@@ -137,7 +137,7 @@ enum { MODE_SMALL = 0, MODE_COLS = 1, MODE_ROWS = 2 };
 
 // ------------------------------------------------------------ compile-time plan
 
-template <int LOG_NU, int LR0, int LR1, int LR2>
+template <int LOG_NU, int LR0, int LR1, int LR2, int LANE = 0>
 struct PassPlan {
     static constexpr int NP = LR1 == 0 ? 1 : (LR2 == 0 ? 2 : 3);
     static constexpr int lr(int p) { return p == 0 ? LR0 : (p == 1 ? LR1 : LR2); }
@@ -149,6 +149,9 @@ struct PassPlan {
     // elements, PAD = M_{p+1} (residues left after the next pass) when that is
     // below 32, which spreads group-fast reads of consecutive columns over banks.
     static constexpr int pad(int p) {
+        // lane-tail units read the last pass column-fast (lane = q + 16 r):
+        // two elements per row keep those reads on distinct banks
+        if (LANE && p + 2 == NP) return 2;
         return (p + 1 < NP && log_m(p + 1) < 5) ? (1 << log_m(p + 1)) : 0;
     }
     static constexpr int padded(int p) {
@@ -230,6 +233,75 @@ __device__ __forceinline__ void stage_out(const E* lds, E* out, int64_t first, i
     }
 }
 
+// ------------------------------------------------------- cross-lane stages
+
+// Exchanges the upper half (D = 32) or the odd rows (D = 16) of x with the
+// lower half / even rows of y (v_permlane32_swap / v_permlane16_swap).
+// Afterwards every lane l holds, in (x, y), the pair (x_lower, x_upper) of
+// lanes (l & ~D, l | D) when l is a lower lane, and (y_lower, y_upper) when
+// l is an upper lane: both operands of one butterfly whose partners are D
+// lanes apart.
+template <int D>
+__device__ __forceinline__ void swap_halves(uint32_t& x, uint32_t& y) {
+    if constexpr (D == 32) {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    } else {
+        static_assert(D == 16, "lane distance 16 or 32");
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    }
+}
+template <int D>
+__device__ __forceinline__ void swap_halves(f2_t& x, f2_t& y) {
+    uint32_t x0 = __builtin_bit_cast(uint32_t, (float)x.x), x1 = __builtin_bit_cast(uint32_t, (float)x.y);
+    uint32_t y0 = __builtin_bit_cast(uint32_t, (float)y.x), y1 = __builtin_bit_cast(uint32_t, (float)y.y);
+    swap_halves<D>(x0, y0);
+    swap_halves<D>(x1, y1);
+    x.x = __builtin_bit_cast(float, x0);
+    x.y = __builtin_bit_cast(float, x1);
+    y.x = __builtin_bit_cast(float, y0);
+    y.y = __builtin_bit_cast(float, y1);
+}
+
+// The last two radix-2 stages of a one-wave unit of NU points, across lanes.
+// On entry lane (u, r, q) = (bit 5, bit 4, bits 0-3) holds v[e] = Y[r'][q + 16 e]
+// with r' = 2u + r (the four residues left) for e < NU/64.
+//   Stage with span NU/2 pairs residues r' and r' + 2 (lanes 32 apart): after
+//   swapping register pairs (v[2k], v[2k+1]), lane (u, r, q) holds a = Y[r][j],
+//   b = Y[r + 2][j] with j = q + 16 (2k + u); A -> v[2k] (= Y'[r][j]),
+//   B -> v[2k+1] (= Y'[r][j + NU/4]).
+//   Stage with span NU pairs residues 0 and 1 (lanes 16 apart): the lane with
+//   r = 0 takes the pair of register v[2k], the lane with r = 1 that of v[2k+1];
+//   the column is jb = q + 16 (2k + u) + (NU/4) r; A -> X[jb], B -> X[jb + NU/2].
+// Every butterfly keeps its operands, table entry (level-ordered index
+// L/2 + j) and FMA order, so the result equals the radix-2 Stockham definition.
+template <class E, int LOG_NU>
+__device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __restrict__ lt,
+                                          int lane) {
+    using TW = typename TwOf<E>::type;
+    constexpr int NU = 1 << LOG_NU;
+    constexpr int EL = NU / 64;
+    const int q = lane & 15, r = (lane >> 4) & 1, u = lane >> 5;
+    TW tw[EL / 2];
+#pragma unroll
+    for (int k = 0; k < EL / 2; ++k) tw[k] = lt[NU / 4 + q + 16 * (2 * k + u)];
+#pragma unroll
+    for (int k = 0; k < EL / 2; ++k) {
+        swap_halves<32>(v[2 * k], v[2 * k + 1]);
+        bfly(v[2 * k], v[2 * k + 1], tw[k]);
+    }
+#pragma unroll
+    for (int k = 0; k < EL / 2; ++k) tw[k] = lt[NU / 2 + q + 16 * (2 * k + u) + (NU / 4) * r];
+#pragma unroll
+    for (int k = 0; k < EL / 2; ++k) {
+        swap_halves<16>(v[2 * k], v[2 * k + 1]);
+        bfly(v[2 * k], v[2 * k + 1], tw[k]);
+    }
+}
+
 // Where the units of one workgroup live: a regular launch takes UPW
 // consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
 // units of one work item (BatchGeo, in fft_batch.hpp).
@@ -251,11 +323,11 @@ struct GridGeo {
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
 // LR radix-2 stages per group, scatter (LDS or global).
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int P, class Geo>
+          int LANE, int P, class Geo>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                           const E* in, E* out, const Geo& gp) {
     using TW = typename TwOf<E>::type;
-    using PP = PassPlan<LOG_NU, LR0, LR1, LR2>;
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NP = PP::NP;
     if constexpr (P < NP) {
         constexpr int NU = 1 << LOG_NU;
@@ -272,7 +344,10 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
         const int tid = threadIdx.x;
         const int ul = unit_fast ? (tid % UPW) : (tid / G);
-        const int g = unit_fast ? (tid / UPW) : (tid % G);
+        const int g0 = unit_fast ? (tid / UPW) : (tid % G);
+        // lane-tail units: the last pass takes group (r, q) on lane q + 16 r
+        constexpr bool lane_map = LANE && P == NP - 1;
+        const int g = lane_map ? (((g0 & 15) << 2) | (g0 >> 4)) : g0;
         const bool active = gp.active(ul);
         E* reg = lds + ul * RS;
         const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul);
@@ -339,7 +414,34 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- scatter
-        if constexpr (P + 1 < NP) {
+        if constexpr (LANE && P == NP - 1) {
+            static_assert(G == 64 && GPL == 1 && M == 4 && L0 == 16 && MODE == MODE_SMALL,
+                          "lane tail needs one wave per unit and a 16 x 4 last pass");
+            lane_tail<E, LOG_NU>(v, lt, g0);
+            // lane (u, r, q) holds X[jb] in v[2k] and X[jb + NU/2] in v[2k+1],
+            // jb = q + 16 (2k + u) + (NU/4) r
+            const int q = g0 & 15, r = (g0 >> 4) & 1, u = g0 >> 5;
+            if constexpr (STG) {
+                __syncthreads();
+                E* nat = lds + ul * NU;
+#pragma unroll
+                for (int k = 0; k < EL / 2; ++k) {
+                    const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
+                    nat[jb] = v[2 * k];
+                    nat[jb + NU / 2] = v[2 * k + 1];
+                }
+                __syncthreads();
+                stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
+                                                   gp.block_units(UPW) << LOG_NU);
+            } else if (active) {
+#pragma unroll
+                for (int k = 0; k < EL / 2; ++k) {
+                    const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
+                    __builtin_nontemporal_store(v[2 * k], out + geo.base_out + jb);
+                    __builtin_nontemporal_store(v[2 * k + 1], out + geo.base_out + jb + NU / 2);
+                }
+            }
+        } else if constexpr (P + 1 < NP) {
             constexpr int PAD = PP::pad(P);
             if constexpr (P > 0 || STG) __syncthreads();   // readers of LDS are done
 #pragma unroll
@@ -378,7 +480,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 }
             }
         }
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, P + 1>(v, lds, lt, in, out, gp);
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, P + 1>(v, lds, lt, in, out,
+                                                                                gp);
     }
 }
 
@@ -386,11 +489,12 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // lt: level-ordered table.  units: units in this launch.  log_m: log2(N/NU),
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG>
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE>
 __global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E))
 fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
-    static_assert(LR0 + LR1 + LR2 == LOG_NU, "radices must multiply to NU");
+    static_assert(LR0 + LR1 + LR2 + 2 * LANE == LOG_NU, "radices must multiply to NU");
     static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
     static_assert(MODE != MODE_ROWS || LR1 > 0, "row units need two passes");
     static_assert(STG == 0 || MODE == MODE_SMALL, "staging needs contiguous units");
@@ -398,7 +502,7 @@ fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ 
     E* lds = reinterpret_cast<E*>(lds_raw);
     E v[1 << LOG_E];
     const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m};
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, 0>(v, lds, lt, in, out, gp);
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 0>(v, lds, lt, in, out, gp);
 }
 
 }  // namespace dsfft

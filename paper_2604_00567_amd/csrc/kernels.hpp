@@ -19,6 +19,7 @@ struct KernelCfg {
     int upw;        // units per workgroup
     int lr[3];      // register-pass radices (log2; 0 = absent)
     int staged;     // 1: block copied through LDS with 16-byte accesses
+    int lane_tail;  // 1: the last two stages run across lanes (permlane swaps)
     int threads;    // workgroup size
     size_t lds_bytes;
     LaunchFn launch;

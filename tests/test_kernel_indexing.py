@@ -21,19 +21,20 @@ MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
 def load_configs():
     out = []
     for line in open(CONFIGS):
-        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+)\)",
-                     line)
+        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
+                     r"\s*(\d+),\s*(\d+)\)", line)
         if m:
             mode = MODES[m.group(1)]
-            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 9)))
+            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 10)))
     return out
 
 
 class PassPlan:
-    def __init__(self, log_nu, lrs):
+    def __init__(self, log_nu, lrs, lane=0):
         self.log_nu = log_nu
         self.lrs = [x for x in lrs if x]
         self.np = len(self.lrs)
+        self.lane = lane
 
     def lr(self, p):
         return self.lrs[p]
@@ -45,6 +46,8 @@ class PassPlan:
         return self.log_nu - self.log_l0(p) - self.lr(p)
 
     def pad(self, p):
+        if self.lane and p + 2 == self.np:
+            return 2
         return (1 << self.log_m(p + 1)) if (p + 1 < self.np and self.log_m(p + 1) < 5) else 0
 
     def padded(self, p):
@@ -70,9 +73,45 @@ def bfly(a, b, w):
     return a + w * b, a - w * b
 
 
+def swap_halves(x, y, d):
+    """Model of v_permlane{32,16}_swap on one wave (64 lanes): lanes whose bit
+    d is clear receive into y the x of lane l + d; lanes with the bit set
+    receive into x the y of lane l - d."""
+    x2, y2 = x.copy(), y.copy()
+    for l in range(64):
+        if l & d:
+            x2[l] = y[l - d]
+        else:
+            y2[l] = x[l + d]
+    return x2, y2
+
+
+def lane_tail_model(v, NU, EL, NT, tcap):
+    """The two cross-lane stages of fft_device.hpp's lane_tail, per wave."""
+    for w0 in range(0, NT, 64):
+        lanes = np.arange(64)
+        q, r, u = lanes & 15, (lanes >> 4) & 1, lanes >> 5
+        for stage, d in ((1, 32), (2, 16)):
+            for k in range(EL // 2):
+                x, y = v[w0:w0 + 64, 2 * k].copy(), v[w0:w0 + 64, 2 * k + 1].copy()
+                x, y = swap_halves(x, y, d)
+                for l in range(64):
+                    if stage == 1:
+                        idx = NU // 4 + q[l] + 16 * (2 * k + u[l])
+                        L_expect = NU // 2
+                    else:
+                        idx = NU // 2 + q[l] + 16 * (2 * k + u[l]) + (NU // 4) * r[l]
+                        L_expect = NU
+                    assert 0 < idx < tcap
+                    w, L, j = level_twiddle(idx)
+                    assert L == L_expect
+                    x[l], y[l] = bfly(x[l], y[l], w)
+                v[w0:w0 + 64, 2 * k], v[w0:w0 + 64, 2 * k + 1] = x, y
+
+
 def simulate(cfg, n, batch, x=None):
-    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg = cfg
-    pp = PassPlan(log_nu, (lr0, lr1, lr2))
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane = cfg
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     NU, EL = 1 << log_nu, 1 << log_e
     G = NU // EL
     NT = upw * G
@@ -102,7 +141,8 @@ def simulate(cfg, n, batch, x=None):
             geos = []
             for tid in range(NT):
                 ul = tid % upw if unit_fast else tid // G
-                g = tid // upw if unit_fast else tid % G
+                g0 = tid // upw if unit_fast else tid % G
+                g = (((g0 & 15) << 2) | (g0 >> 4)) if (lane and p == pp.np - 1) else g0
                 unit = blk * upw + ul
                 active = unit < units
                 reg = ul * RS
@@ -181,10 +221,26 @@ def simulate(cfg, n, batch, x=None):
                     vv[u * R:(u + 1) * R] = grp
                 newv[tid] = vv
                 geos.append((ul, g, active, reg, base_out, out_s))
+            if lane and p == pp.np - 1:
+                assert G == 64 and GPL == 1 and M == 4 and L0 == 16 and mode == 0
+                lane_tail_model(newv, NU, EL, NT, tcap)
             # every lane has gathered before any lane scatters (the kernel's barrier)
             for tid in range(NT):
                 ul, g, active, reg, base_out, out_s = geos[tid]
                 vv = newv[tid]
+                if lane and p == pp.np - 1:
+                    g0 = tid % G
+                    q, r, u = g0 & 15, (g0 >> 4) & 1, g0 >> 5
+                    for k in range(EL // 2):
+                        jb = q + 16 * (2 * k + u) + (NU // 4) * r
+                        for idx, val in ((jb, vv[2 * k]), (jb + NU // 2, vv[2 * k + 1])):
+                            assert idx < NU
+                            if active:
+                                a = base_out + idx
+                                assert 0 <= a < batch * n
+                                out[a] = val
+                                written[a] += 1
+                    continue
                 if p + 1 < pp.np:
                     pad = pp.pad(p)
                     for u in range(GPL):
