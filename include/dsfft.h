@@ -126,6 +126,24 @@ int fft_plan_set_workspace(fft_plan* plan, void* dev_ptr, size_t bytes);
 fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
                                   int variant_a, int variant_b, int two_pass);
 
+/*
+ * Autotuner: times every compiled configuration for (n, dtype) -- register-
+ * pass radices (fusion depth), units per workgroup (LDS tile), elements per
+ * lane (waves per transform), LDS staging, cross-lane tail, single-kernel or
+ * two-pass -- on `batch` synthetic transforms with HIP events (`reps` timed
+ * executions each), accepts a candidate only if its output is bit-identical
+ * to the default configuration's, and records the fastest: later
+ * fft_plan_create calls for this (n, dtype) in the process use it, and the
+ * record is appended to the file named by the DSFFT_TUNE_FILE environment
+ * variable (read back at the first plan creation of a process).  `report`
+ * receives a JSON array of the candidates' timings (up to `cap` bytes).
+ */
+int fft_tune(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind, int reps,
+             char* report, size_t cap);
+
+/* The recorded tuning choice for (n, dtype); FFT_EINVAL if none. */
+int fft_tuned_choice(int64_t n, fft_dtype dtype, int* variant_a, int* variant_b, int* two_pass);
+
 /* Number of compiled configurations for (n, dtype): *single for the
  * one-kernel schedule, *cols and *rows for the two kernels of the two-pass one. */
 int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows);
@@ -149,6 +167,12 @@ fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, ff
  * select the alternative configuration (0 or 1) for N = 2^10 / 2^12. */
 fft_batch* fft_batch_create_tuned(const int64_t* n, int64_t count, fft_dtype dtype,
                                   fft_table_kind kind, int choice_1024, int choice_4096);
+
+/* Tuner for the uneven batch: times the alternatives for the 2^10 and 2^12
+ * size classes (class-only batches, `reps` replays, outputs required to be
+ * bit-identical) and returns the faster choice of each (0 or 1). */
+int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1024,
+                   int* choice_4096);
 
 /* Enqueues the whole uneven batch on `stream` (device pointers, packed
  * layout, element-aligned; in == out allowed).  Async. */

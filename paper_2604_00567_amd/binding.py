@@ -61,6 +61,10 @@ _SIGS = {
     "fft_batch_status": ([_vp, ctypes.POINTER(_int)], _int),
     "fft_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
     "fft_batch_destroy": ([_vp], None),
+    "fft_tune": ([_i64, _i64, _int, _int, _int, ctypes.c_char_p, _sz], _int),
+    "fft_tuned_choice": ([_i64, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
+                          ctypes.POINTER(_int)], _int),
+    "fft_batch_tune": ([_int, _int, _int, ctypes.POINTER(_int), ctypes.POINTER(_int)], _int),
     "fft_serve_slot_create": ([_int, _int, _i64, _i64, _int, _sz], _vp),
     "fft_serve_slot_launch": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
     "fft_serve_slot_query": ([_vp], _int),
@@ -160,6 +164,28 @@ def fft_config_count(n: int, dtype) -> tuple[int, int, int]:
     a, b, c = _int(), _int(), _int()
     _check(_lib.fft_config_count(n, _dt(dtype), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
     return a.value, b.value, c.value
+
+
+def fft_tune(n: int, batch: int, dtype, kind="dual_select", reps: int = 10) -> list:
+    """Times every configuration for (n, dtype); returns the candidates' report."""
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    _check(_lib.fft_tune(n, batch, _dt(dtype), _kd(kind), reps, buf, 1 << 16))
+    return json.loads(buf.value.decode())
+
+
+def fft_tuned_choice(n: int, dtype):
+    a, b, t = _int(), _int(), _int()
+    rc = _lib.fft_tuned_choice(n, _dt(dtype), ctypes.byref(a), ctypes.byref(b), ctypes.byref(t))
+    if rc != FFT_OK:
+        return None
+    return a.value, b.value, bool(t.value)
+
+
+def fft_batch_tune(dtype, kind="dual_select", reps: int = 5) -> tuple[int, int]:
+    a, b = _int(), _int()
+    _check(_lib.fft_batch_tune(_dt(dtype), _kd(kind), reps, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def fft_batch_create(sizes, dtype, kind, choice=None) -> int:

