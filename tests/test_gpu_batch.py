@@ -115,6 +115,6 @@ def test_tuned_alternatives_bit_identical(choice):
 
 
 def test_batch_argument_errors():
-    for bad in ([3], [1 << 17], [0], []):
+    for bad in ([3], [1 << 19], [0], []):
         with pytest.raises(binding.FFTError):
             binding.fft_batch_create(np.array(bad, dtype=np.int64), "f16", "dual_select")
