@@ -110,9 +110,10 @@ std::string describe(const KernelCfg* k) {
     if (!k) return "none";
     static const char* modes[] = {"small", "cols", "rows"};
     char buf[160];
-    std::snprintf(buf, sizeof buf, "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],stg=%d,t=%d,lds=%zu",
+    std::snprintf(buf, sizeof buf,
+                  "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],stg=%d,lane=%d,pipe=%d,t=%d,lds=%zu",
                   modes[k->mode], k->log_nu, k->log_e, k->upw, k->lr[0], k->lr[1], k->lr[2],
-                  k->staged, k->threads, k->lds_bytes);
+                  k->staged, k->lane_tail, k->pipelined, k->threads, k->lds_bytes);
     return buf;
 }
 

@@ -73,7 +73,7 @@ __device__ __forceinline__ void batch_unit(E* v, E* lds, const typename TwOf<E>:
                                            const E* src, E* dst, const BatchGeo& geo) {
     static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 256 threads");
     static_assert((1 << LOG_E) <= kBatchMaxElems, "too many elements per lane");
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0, 0>(v, lds, lt, src, dst, geo);
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, geo);
 }
 
 // Largest LDS footprint over the batch configurations, in elements.

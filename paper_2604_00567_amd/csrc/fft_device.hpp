@@ -320,10 +320,45 @@ struct GridGeo {
     }
 };
 
+// Pass-0 inputs of this lane straight from HBM (unstaged configurations):
+// group r = g + G u (residue r, span 1) takes elements r + M i, i < R.
+// The streaming hint is used only where a wave's accesses cover whole lines.
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int LANE,
+          class Geo>
+__device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+    constexpr int NU = 1 << LOG_NU;
+    constexpr int EL = 1 << LOG_E;
+    constexpr int G = NU / EL;
+    constexpr int R = 1 << PP::lr(0);
+    constexpr int M = 1 << PP::log_m(0);
+    constexpr int GPL = EL / R;
+    constexpr bool unit_fast = (MODE == MODE_COLS);
+    const int tid = threadIdx.x;
+    const int ul = unit_fast ? (tid % UPW) : (tid / G);
+    const int g = unit_fast ? (tid / UPW) : (tid % G);
+    if (gp.active(ul)) {
+        const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul);
+#pragma unroll
+        for (int u = 0; u < GPL; ++u) {
+            const int r = g + G * u;
+#pragma unroll
+            for (int i = 0; i < R; ++i) {
+                const int64_t idx = r + (int64_t)M * i;
+                const E* src = in + geo.base_in + idx * geo.in_stride;
+                v[u * R + i] = (MODE != MODE_COLS) ? __builtin_nontemporal_load(src) : *src;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < EL; ++k) v[k] = E{};
+    }
+}
+
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
 // LR radix-2 stages per group, scatter (LDS or global).
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int P, class Geo>
+          int LANE, int PRE, int P, class Geo>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                           const E* in, E* out, const Geo& gp) {
     using TW = typename TwOf<E>::type;
@@ -367,20 +402,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 for (int i = 0; i < R; ++i) v[u * R + i] = nat[r + M * i];
             }
         } else if constexpr (P == 0) {
-            if (active) {
-#pragma unroll
-                for (int u = 0; u < GPL; ++u) {
-                    const int r = g + G * u;      // residue; span 1 so column 0
-#pragma unroll
-                    for (int i = 0; i < R; ++i) {
-                        const int64_t idx = r + (int64_t)M * i;
-                        v[u * R + i] = __builtin_nontemporal_load(in + geo.base_in + idx * geo.in_stride);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int k = 0; k < EL; ++k) v[k] = E{};
-            }
+            if constexpr (!PRE) load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(v, in, gp);
         } else {
             constexpr int PADP = PP::pad(P - 1);
 #pragma unroll
@@ -475,13 +497,15 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                     for (int e = 0; e < R; ++e) {
                         const int64_t idx = q + (int64_t)L0 * e;
-                        __builtin_nontemporal_store(v[u * R + e], out + geo.base_out + idx * geo.out_stride);
+                        E* dst = out + geo.base_out + idx * geo.out_stride;
+                        if (MODE == MODE_SMALL) __builtin_nontemporal_store(v[u * R + e], dst);
+                        else *dst = v[u * R + e];
                     }
                 }
             }
         }
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, P + 1>(v, lds, lt, in, out,
-                                                                                gp);
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PRE, P + 1>(v, lds, lt, in,
+                                                                                     out, gp);
     }
 }
 
@@ -490,19 +514,78 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE>
+          int LANE, int PIPE>
+__device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
+                                                 const typename TwOf<E>::type* __restrict__ lt,
+                                                 int64_t units, int log_m);
+
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
 __global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E))
 fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
+                                                                                  units, log_m);
+}
+
+// The pipelined kernel holds two register sets; the compiler is asked to fit
+// three waves per SIMD so the prefetch is not bought with occupancy.
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
+__global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
+fft_unit_kernel_pipe(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
+                     int64_t units, int log_m) {
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
+                                                                                  units, log_m);
+}
+
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
+__device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
+                                                 const typename TwOf<E>::type* __restrict__ lt,
+                                                 int64_t units, int log_m) {
     static_assert(LR0 + LR1 + LR2 + 2 * LANE == LOG_NU, "radices must multiply to NU");
     static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
     static_assert(MODE != MODE_ROWS || LR1 > 0, "row units need two passes");
     static_assert(STG == 0 || MODE == MODE_SMALL, "staging needs contiguous units");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
+    static_assert(PIPE == 0 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
     E v[1 << LOG_E];
-    const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m};
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 0>(v, lds, lt, in, out, gp);
+    if constexpr (PIPE) {
+        // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
+        // in two register sets used alternately (a and b), so the next block's
+        // HBM reads are in flight while the current block is computed and no
+        // register copy forces an early wait
+        E vb[1 << LOG_E];
+        const int64_t nblk = (units + UPW - 1) / UPW;
+        const int64_t step = gridDim.x;
+        int64_t blk = blockIdx.x;
+        if (blk < nblk)
+            load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+                v, in, GridGeo{blk * UPW, units, log_m});
+        while (blk < nblk) {
+            if (blk + step < nblk)
+                load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+                    vb, in, GridGeo{(blk + step) * UPW, units, log_m});
+            unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
+                v, lds, lt, in, out, GridGeo{blk * UPW, units, log_m});
+            __syncthreads();    // LDS is reused by the next block
+            blk += step;
+            if (blk >= nblk) break;
+            if (blk + step < nblk)
+                load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+                    v, in, GridGeo{(blk + step) * UPW, units, log_m});
+            unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
+                vb, lds, lt, in, out, GridGeo{blk * UPW, units, log_m});
+            __syncthreads();
+            blk += step;
+        }
+    } else {
+        const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m};
+        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
+                                                                               gp);
+    }
 }
 
 }  // namespace dsfft

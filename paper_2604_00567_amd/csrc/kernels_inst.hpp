@@ -6,29 +6,53 @@
 
 namespace dsfft {
 
+// The kernel entry for a configuration: the pipelined entry (with its
+// occupancy attribute) only where PIPE is set.
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE>
+          int LANE, int PIPE>
+static constexpr auto kernel_entry() {
+    if constexpr (PIPE)
+        return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
+    else
+        return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
+}
+
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
     using TW = typename TwOf<E>::type;
     constexpr int NT = UPW << (LOG_NU - LOG_E);
     constexpr size_t LDS =
         (size_t)UPW * PassPlan<LOG_NU, LR0, LR1, LR2, LANE>::region() * sizeof(E);
-    const int64_t grid = (units + UPW - 1) / UPW;
+    auto kern = kernel_entry<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+    int64_t grid = (units + UPW - 1) / UPW;
     if (grid <= 0) return hipSuccess;
+    if (PIPE) {
+        // persistent grid: the workgroups that fit on the device at once
+        static int resident = 0;
+        if (!resident) {
+            int dev = 0, cus = 0, per = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, NT, LDS) != hipSuccess)
+                return hipErrorInvalidConfiguration;
+            resident = cus * (per > 0 ? per : 1);
+        }
+        grid = grid < resident ? grid : resident;
+    }
     if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL((fft_unit_kernel<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE>),
-                       dim3((unsigned)grid), dim3(NT), LDS, stream, (const E*)in, (E*)out,
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), LDS, stream, (const E*)in, (E*)out,
                        (const TW*)lt, units, log_m);
     return hipGetLastError();
 }
 
-#define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE)                                \
-    {DTYPE_ID, MODE, LOG_NU, LOG_E, UPW, {LR0, LR1, LR2}, STG, LANE,                           \
+#define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE)                          \
+    {DTYPE_ID, MODE, LOG_NU, LOG_E, UPW, {LR0, LR1, LR2}, STG, LANE, PIPE,                     \
      (UPW) << ((LOG_NU) - (LOG_E)),                                                            \
      (size_t)(UPW) * PassPlan<LOG_NU, LR0, LR1, LR2, LANE>::region() * sizeof(ELEM_T),         \
-     &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE>,                 \
-     (const void*)&fft_unit_kernel<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE>},
+     &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>,           \
+     (const void*)kernel_entry<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()},
 
 static const KernelCfg kTable[] = {
 #include "configs.inc"
