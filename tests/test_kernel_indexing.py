@@ -22,9 +22,11 @@ def load_configs():
     out = []
     for line in open(CONFIGS):
         m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
-                     r"\s*(\d+),\s*(\d+)\)", line)
+                     r"\s*(\d+),\s*(\d+),\s*(\d+)\)", line)
         if m:
             mode = MODES[m.group(1)]
+            # the pipelined flag changes which workgroup takes a block, not a
+            # block's index math (blocks b, b + grid, ... cover every block once)
             out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 10)))
     return out
 
@@ -277,6 +279,20 @@ def test_small_configs_index_math(cfg):
     assert np.all(written == 1)
     ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
     assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+def test_configs_parsed():
+    cfgs = load_configs()
+    text = open(CONFIGS).read()
+    assert len(cfgs) == text.count("\nCFG(") and len(cfgs) > 40
+
+
+def test_persistent_blocks_cover_once():
+    for nblk in (1, 7, 256, 1000):
+        for grid in (1, 3, 256, 2048):
+            g = min(grid, nblk)
+            seen = [b for w in range(g) for b in range(w, nblk, g)]
+            assert sorted(seen) == list(range(nblk))
 
 
 @pytest.mark.parametrize("m1,m2", [(6, 6), (7, 6), (7, 7), (8, 6)])
