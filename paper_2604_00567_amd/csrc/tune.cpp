@@ -4,7 +4,10 @@
 // same butterflies, so any difference is a defect), and records the fastest
 // in a process-wide registry that plan creation consults.  Records persist in
 // a plain-text file named by DSFFT_TUNE_FILE (one record per line:
-// "arch cus dtype log2n variant_a variant_b two_pass GB/s").
+// "arch cus dtype log2n variant_a variant_b two_pass GB/s").  Records shipped
+// with the library (tuning_records.txt beside libdsfft.so, measured on the
+// target device) are read first; DSFFT_TUNE_FILE records override them.
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,14 +47,9 @@ static std::string device_tag() {
     return arch + " " + std::to_string(prop.multiProcessorCount);
 }
 
-static void load_records_locked() {
-    if (g_tune_loaded) return;
-    g_tune_loaded = true;
-    const char* path = std::getenv("DSFFT_TUNE_FILE");
-    if (!path) return;
-    FILE* f = std::fopen(path, "r");
+static void read_records(const std::string& path, const std::string& tag) {
+    FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return;
-    const std::string tag = device_tag();
     char arch[64];
     int cus, dt, m, va, vb, two;
     double gbs;
@@ -60,6 +58,24 @@ static void load_records_locked() {
         g_tuned[std::make_tuple(dt, m)] = TuneRec{va, vb, two, gbs};
     }
     std::fclose(f);
+}
+
+// tuning_records.txt in the directory holding this library
+static std::string shipped_records() {
+    Dl_info info;
+    if (!dladdr((void*)&shipped_records, &info) || !info.dli_fname) return "";
+    std::string p = info.dli_fname;
+    const size_t slash = p.rfind('/');
+    return (slash == std::string::npos ? std::string() : p.substr(0, slash + 1)) + "tuning_records.txt";
+}
+
+static void load_records_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const std::string tag = device_tag();
+    const std::string shipped = shipped_records();
+    if (!shipped.empty()) read_records(shipped, tag);
+    if (const char* path = std::getenv("DSFFT_TUNE_FILE")) read_records(path, tag);
 }
 
 // The tuned choice for (dtype, log2 n), if any: variants[3] = {a, b, two_pass}.
