@@ -31,6 +31,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 EB = {"f16": 4, "f32": 8}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "fft_unit_n1024x65536_f16_traffic.txt")
+# sources that define the unit kernels: a change to any of them invalidates
+# counter readings taken before it
+KERNEL_SOURCES = ["fft_device.hpp", "kernels.hpp", "kernels_inst.hpp", "kernels_f16.hip",
+                  "configs.inc"]
 
 
 def log(msg: str) -> None:
@@ -66,7 +71,7 @@ def timed_loop(torch, run, nsets: int, steps: int, warmup: int):
 
 
 def time_plan(torch, binding, inputs, n, batch, dtype, kind, steps, warmup, seed, gen="uniform",
-              distinct=None):
+              distinct=None, keep=None):
     """Times a plan on rotating buffer sets.  With `distinct`, only that many
     transforms are generated and tiled to the batch on the device (the data
     values do not change the timing; the error sample uses the generated ones)."""
@@ -86,9 +91,67 @@ def time_plan(torch, binding, inputs, n, batch, dtype, kind, steps, warmup, seed
            "gbs": algo / wall / 1e9, "gbs_kernel": algo / dev / 1e9,
            "transforms_per_s": batch / wall, "algo_bytes": algo,
            "config": plan.info()["config"], "buffer_sets": len(xs)}
-    last = ys[(steps - 1) % len(xs)]
+    last = ys[(steps - 1) % len(xs)].clone()
+    if keep is not None:
+        med, mn = per_launch_ms(torch, lambda i: plan.execute(xs[i], ys[i]), len(xs))
+        res["per_launch_ms"] = {"median": med, "min": mn, "reps": 20}
+        keep["xs"], keep["ys"] = xs, ys
     plan.close()
     return res, x0, last
+
+
+def time_kinds(torch, binding, xs, ys, n, batch, dtype, steps, warmup):
+    """The same kernel with each table kind (the path encoding lives in the
+    table, so the instruction stream is identical): mean ms per execute."""
+    out = {}
+    for kind in ("dual_select", "linzer_feig", "cosine", "lf_w0_exempt"):
+        plan = binding.Plan(n, batch, dtype, kind)
+        _, dev = timed_loop(torch, lambda i: plan.execute(xs[i], ys[i]), len(xs), steps, warmup)
+        out[kind] = {"kernel_ms": round(dev * 1e3, 4),
+                     "gbs": round(2.0 * n * batch * EB[dtype] / dev / 1e9, 1)}
+        plan.close()
+    return out
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2604_00567_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel_config: str):
+    """HBM bytes per launch of the headline kernel from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a
+    256 MiB device copy), or None when there is no summary, it covers another
+    configuration, or the kernel sources changed after it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            kv = dict(line.split(": ", 1) for line in fh.read().splitlines()
+                      if ": " in line and not line.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel", "").strip() != kernel_config:
+        return None
+    if kv.get("sources_sha256", "").strip() != kernel_sources_sha256():
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def per_launch_ms(torch, run, nsets: int, reps: int = 20):
+    """Median and minimum of single launches, each between its own event pair."""
+    ts = []
+    for i in range(reps):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        run(i % nsets)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    return float(np.median(ts)), float(np.min(ts))
 
 
 def error_vs_fp64(x: np.ndarray, y: np.ndarray):
@@ -121,7 +184,6 @@ def bench_uneven(torch, binding, inputs, steps, warmup):
     xs, ys = rotating_sets(torch, x0, min_bytes=0.8e9)
     b = binding.Batch(sizes, "f16", "dual_select")
     wall, dev = timed_loop(torch, lambda i: b.execute(xs[i], ys[i]), len(xs), steps, warmup)
-    assert b.status() == 0
     info = b.info()
     b.close()
     algo = 2.0 * float(np.sum(sizes)) * 4
@@ -246,9 +308,14 @@ def main():
 
     from paper_2604_00567_amd import binding, inputs
 
+    # Everything runs on a dedicated stream: launches on the legacy default
+    # stream pay for its implicit ordering with every other stream.
+    torch.cuda.set_stream(torch.cuda.Stream())
+
     log("timing N=1024 x 65536 f16 dual-select")
+    bufs = {}
     main_res, x0, yout = time_plan(torch, binding, inputs, 1024, 65536, "f16", "dual_select",
-                                   args.steps, args.warmup, seed=2)
+                                   args.steps, args.warmup, seed=2, keep=bufs)
     log(f"N=1024: {main_res['gbs']:.0f} GB/s wall, {main_res['gbs_kernel']:.0f} GB/s device")
     pick = np.random.default_rng(3).choice(65536, 256, replace=False)
     err = error_vs_fp64(x0[pick], yout.cpu().numpy()[pick])
@@ -274,8 +341,10 @@ def main():
         "transforms_per_s": round(main_res["transforms_per_s"]),
         "roofline": {"bound": "hbm", "achieved": round(main_res["gbs_kernel"], 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(main_res["gbs_kernel"] / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(main_res["gbs_kernel"] / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(main_res["config"]),
                      "kernel_ms_mean": round(main_res["kernel_ms"], 4),
+                     "per_launch_ms": main_res["per_launch_ms"],
                      "algo_bytes_per_launch": main_res["algo_bytes"]},
         "error_vs_fp64": dict(err, bound=(1 + 2.0 ** -11) ** 10 - 1, sample_transforms=len(pick)),
     }
@@ -287,6 +356,9 @@ def main():
         lf["dual_select_vs_lf_w0_exempt_max_abs_ratio"] = (
             lf["lf_w0_exempt"]["max_abs"] / ds_max if ds_max else None)
         result["comparison_tables"] = lf
+        log("same kernel, each table kind")
+        result["table_kind_timing"] = time_kinds(torch, binding, bufs["xs"], bufs["ys"], 1024, 65536,
+                                                 "f16", args.steps, args.warmup)
         del yout
         log("timing N=4096 x 16384 f16 dual-select")
         sec, x02, y2 = time_plan(torch, binding, inputs, 4096, 16384, "f16", "dual_select",
@@ -313,6 +385,7 @@ def main():
         if args.serve_seconds > 0:
             log(f"serving, {args.serve_seconds:g} s of trace")
             result["serving"] = bench_serving(torch, args.serve_seconds)
+    bufs.clear()
     if not args.no_cpu:
         log("cpu baseline (oracle emulation)")
         result["cpu_baseline"] = cpu_baseline(x0, 1024, args.cpu_seconds)

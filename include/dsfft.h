@@ -88,7 +88,11 @@ fft_plan* fft_plan_create(int64_t n, int64_t batch, fft_dtype dtype, fft_table_k
  */
 int fft_execute(fft_plan* plan, const void* in, void* out, void* stream);
 
-/* Waits for the plan's last execution, then frees it.  NULL-safe. */
+/* Frees the plan.  A two-pass plan first waits for its last execution (its
+ * workspace may still be in use); a single-pass plan holds no device memory
+ * that its launches read or write (twiddle tables are shared and live until
+ * the process ends), so it returns at once and launches already enqueued
+ * complete normally.  NULL-safe. */
 void fft_destroy(fft_plan* plan);
 
 /*
@@ -153,13 +157,15 @@ int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* ro
  * 2 .. 2^18), packed back to back in the order given (transform i starts at
  * element sum_{j<i} n[j]).  Every transform is computed exactly as
  * fft_plan_create would (same butterflies, same table), but all of them run
- * in one persistent work-queue kernel launch: sizes up to 2^13 as whole-
- * transform work items, 2^14 .. 2^18 as column items then row items of the
- * two-pass schedule, ordered through per-transform counters in device memory.
- * The launch (a control-block clear plus the kernel) is captured once in a
- * HIP graph and replayed by every execute; new data pointers are patched into
- * the captured kernel node.  The batch owns a workspace of sum of the sizes
- * >= 2^14 elements.  Returns NULL on error.
+ * in two persistent work-queue kernels: sizes up to 2^13 as whole-transform
+ * work items, 2^14 .. 2^18 as the column items and row items of the
+ * two-pass schedule.  The first kernel runs every column item and every
+ * whole-transform item, the second every row item; the launch boundary
+ * orders each transform's row items after its column items.  The three
+ * launches (queue-head reset, first kernel, second kernel) form one HIP graph
+ * built at the first execute and replayed by every execute; new data
+ * pointers are set on the graph's kernel nodes.  The batch owns a workspace
+ * of sum of the sizes >= 2^14 elements.  Returns NULL on error.
  */
 fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, fft_table_kind kind);
 
@@ -181,19 +187,32 @@ int fft_batch_execute(fft_batch* batch, const void* in, void* out, void* stream)
 /* Total elements of the packed layout. */
 int fft_batch_elements(const fft_batch* batch, int64_t* elements);
 
-/* Waits for the last execution and returns its status flags (0 = clean;
- * bit 0 = a bounded dependency wait expired, results are not valid). */
-int fft_batch_status(fft_batch* batch, int* flags);
-
-/* Work items, persistent grid size and workspace bytes of the batch. */
+/* Work items, persistent grid size (the larger of the two kernels') and
+ * workspace bytes of the batch. */
 int fft_batch_info(const fft_batch* batch, int64_t* items, int64_t* grid, size_t* workspace_bytes);
 
 /* Waits for the batch's last execution, then frees it.  NULL-safe. */
 void fft_batch_destroy(fft_batch* batch);
 
+/* The work list an uneven batch of sizes n[0..count) would run (host only,
+ * no device call), for inspection and tests.  Transforms are packed in order
+ * (offsets are prefix sums).  items_out receives 8 int64 per item: config
+ * id, units, first unit (whole-transform items: first index into offs_out;
+ * column and row items: first column or row), log2 of the column/row
+ * count, phase (0: first kernel, 1: second kernel), large-transform index
+ * (-1 for whole-transform items), input offset, output offset (column items
+ * write, and row items read, the workspace).  The first *phase0 items are
+ * phase 0.  offs_out receives the transform offsets of the whole-transform
+ * items.  nitems, phase0, noffs and ws_elems (workspace elements) are always
+ * set; with both output pointers NULL the call only reports the sizes;
+ * FFT_EINVAL when a capacity is too small. */
+int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int64_t item_cap,
+                        int64_t* nitems, int64_t* phase0, int64_t* offs_out, int64_t offs_cap,
+                        int64_t* noffs, int64_t* ws_elems);
+
 /*
  * Serving slot: the device and pinned buffers for one in-flight launch of the
- * uneven-batch kernel over the requests admitted in one scheduling step of a
+ * uneven-batch kernels over the requests admitted in one scheduling step of a
  * continuous-batching server (the same butterflies and tables as every other
  * entry point).  Capacities: max_items work items, max_transforms
  * single-unit transforms, max_large transforms of 2^14 points or more, and
@@ -214,9 +233,6 @@ int fft_serve_slot_launch(fft_serve_slot* slot, const int64_t* n, const int64_t*
 /* 1 if the slot's last launch has finished (or none was made), 0 if running,
  * negative on error. */
 int fft_serve_slot_query(fft_serve_slot* slot);
-
-/* Waits for the slot's last launch and returns its status flags (0 = clean). */
-int fft_serve_slot_status(fft_serve_slot* slot, int* flags);
 
 /* Waits for the slot's last launch, then frees it.  NULL-safe. */
 void fft_serve_slot_destroy(fft_serve_slot* slot);

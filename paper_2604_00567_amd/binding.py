@@ -58,9 +58,10 @@ _SIGS = {
     "fft_batch_create_tuned": ([_vp, _i64, _int, _int, _int, _int], _vp),
     "fft_batch_execute": ([_vp, _vp, _vp, _vp], _int),
     "fft_batch_elements": ([_vp, ctypes.POINTER(_i64)], _int),
-    "fft_batch_status": ([_vp, ctypes.POINTER(_int)], _int),
     "fft_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
     "fft_batch_destroy": ([_vp], None),
+    "fft_batch_work_list": ([_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp,
+                             _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _int),
     "fft_tune": ([_i64, _i64, _int, _int, _int, ctypes.c_char_p, _sz], _int),
     "fft_tuned_choice": ([_i64, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
                           ctypes.POINTER(_int)], _int),
@@ -68,7 +69,6 @@ _SIGS = {
     "fft_serve_slot_create": ([_int, _int, _i64, _i64, _int, _sz], _vp),
     "fft_serve_slot_launch": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
     "fft_serve_slot_query": ([_vp], _int),
-    "fft_serve_slot_status": ([_vp, ctypes.POINTER(_int)], _int),
     "fft_serve_slot_destroy": ([_vp], None),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -210,12 +210,6 @@ def fft_batch_elements(batch: int) -> int:
     return v.value
 
 
-def fft_batch_status(batch: int) -> int:
-    v = _int()
-    _check(_lib.fft_batch_status(batch, ctypes.byref(v)))
-    return v.value
-
-
 def fft_batch_info(batch: int) -> dict:
     it, gr, ws = _i64(), _i64(), _sz()
     _check(_lib.fft_batch_info(batch, ctypes.byref(it), ctypes.byref(gr), ctypes.byref(ws)))
@@ -224,6 +218,25 @@ def fft_batch_info(batch: int) -> dict:
 
 def fft_batch_destroy(batch: int) -> None:
     _lib.fft_batch_destroy(batch)
+
+
+WORK_FIELDS = ("cfg", "nunits", "first", "log_m", "phase", "slot", "in_off", "out_off")
+
+
+def fft_batch_work_list(sizes):
+    """The work list of an uneven batch (host only): (items (k, 8) int64 with
+    columns WORK_FIELDS, number of phase-0 items, whole-transform offsets,
+    workspace elements)."""
+    arr = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
+    ni, p0, no, ws = _i64(), _i64(), _i64(), _i64()
+    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, None, 0, ctypes.byref(ni),
+                                    ctypes.byref(p0), None, 0, ctypes.byref(no), ctypes.byref(ws)))
+    items = np.zeros((ni.value, 8), np.int64)
+    offs = np.zeros(max(1, no.value), np.int64)
+    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, items.ctypes.data, ni.value,
+                                    ctypes.byref(ni), ctypes.byref(p0), offs.ctypes.data, offs.size,
+                                    ctypes.byref(no), ctypes.byref(ws)))
+    return items, p0.value, offs[:no.value], ws.value
 
 
 def fft_serve_slot_create(dtype, kind, max_items: int, max_transforms: int, max_large: int,
@@ -249,12 +262,6 @@ def fft_serve_slot_query(slot: int) -> bool:
     if rc < 0:
         raise FFTError(rc, fft_last_error())
     return rc == 1
-
-
-def fft_serve_slot_status(slot: int) -> int:
-    v = _int()
-    _check(_lib.fft_serve_slot_status(slot, ctypes.byref(v)))
-    return v.value
 
 
 def fft_serve_slot_destroy(slot: int) -> None:
@@ -330,9 +337,6 @@ class Batch:
         _check_tensor(x, self.total, 1, self.dtype)
         _check_tensor(y, self.total, 1, self.dtype)
         fft_batch_execute(self.handle, x.data_ptr(), y.data_ptr(), _torch_stream(stream))
-
-    def status(self) -> int:
-        return fft_batch_status(self.handle)
 
     def info(self) -> dict:
         return fft_batch_info(self.handle)

@@ -44,6 +44,8 @@ static std::map<std::tuple<int, int, int>, std::shared_ptr<DeviceTable>> g_table
 // Level-ordered table with capacity >= n for (device, dtype, kind), shared by
 // every plan that needs it.  A larger request replaces the cached table; plans
 // holding the old one keep it alive.
+static std::vector<std::shared_ptr<DeviceTable>> g_retired_tables;
+
 int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -68,6 +70,12 @@ int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out)
     }
     e = hipMemcpy(t->ptr, img.data(), img.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "hipMemcpy(table)");
+    // A replaced (smaller) table is kept until the process ends: kernels
+    // already enqueued by plans of any lifetime may still read it, and plans
+    // do not wait for their last launch when they are destroyed.  Capacities
+    // grow by powers of two, so all retired tables together are smaller than
+    // the current one.
+    if (it != g_tables.end()) g_retired_tables.push_back(it->second);
     g_tables[key] = t;
     *out = t;
     return FFT_OK;
@@ -255,8 +263,13 @@ int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s) {
         return set_error(FFT_EINVAL, "in and out partially overlap");
     int rc = launch_plan(p, in, out, s);
     if (rc != FFT_OK) return rc;
-    hipError_t e = hipEventRecord(p->last, s);
-    if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    // Only a two-pass plan holds memory that its launches use and that it may
+    // free or replace (the workspace), so only its last launch is tracked;
+    // an event record per execute costs a few microseconds of device time.
+    if (p->k2) {
+        hipError_t e = hipEventRecord(p->last, s);
+        if (e != hipSuccess) return hip_error(e, "hipEventRecord");
+    }
     return FFT_OK;
 }
 

@@ -1,5 +1,5 @@
-// Uneven-size batch plans: work-item construction, HIP graph capture and
-// replay of the persistent kernel (fft_batch.hpp), per-class tuning.
+// Uneven-size batch plans: work-item construction, the HIP graph of the two
+// persistent-kernel phases (fft_batch.hpp) and its replay.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,11 +48,11 @@ struct fft_batch {
     unsigned* d_ctl = nullptr;
     void* ws = nullptr;
     size_t ws_bytes = 0;
-    int nslots = 0, ctl_words = 0, grid = 0;
-    hipStream_t cap_stream = nullptr;
+    int64_t phase0 = 0;                    // items of phase 0 (the rest are phase 1)
+    int grid = 0, grid0 = 0, grid1 = 0, resident = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    hipGraphNode_t knode = nullptr;
+    hipGraphNode_t knode[2] = {nullptr, nullptr};
     const void* cap_in = nullptr;
     void* cap_out = nullptr;
     hipEvent_t last = nullptr;
@@ -66,7 +66,6 @@ fft_batch::~fft_batch() {
     }
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (d_items) (void)hipFree(d_items);
     if (d_offs) (void)hipFree(d_offs);
     if (d_ctl) (void)hipFree(d_ctl);
@@ -90,17 +89,17 @@ static Split split_for(int m) {
     }
 }
 
-// Work items for transforms of sizes n[t] at element offsets off[t]: column
-// items of every large transform first, then single-unit items from the
-// largest size down, then row items (which wait on their transform's column
-// items, all queued earlier).  Large transforms take consecutive workspace
-// slices; ws_elems returns their total, nslots the number of counters.
+// Work items for transforms of sizes n[t] at element offsets off[t]:
+// phase 0 = the column items of every large transform (in input order), then
+// the single-unit items from the largest size down (so the end of the phase
+// is made of short items); phase 1 = the row items.  Large transforms take
+// consecutive workspace slices; ws_elems returns their total.
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
                 std::vector<HostBatchItem>& items, std::vector<int64_t>& offs, int64_t& ws_elems,
-                int& nslots) {
+                int64_t& phase0) {
     items.clear();
     offs.clear();
-    std::vector<HostBatchItem> cols, rows, small;
+    std::vector<HostBatchItem> rows;
     std::vector<std::vector<int64_t>> by_class(19);
     ws_elems = 0;
     int slot = 0;
@@ -114,18 +113,17 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
         const Split sp = split_for(m);
         const int cu = cfg_upw(sp.ccfg), ru = cfg_upw(sp.rcfg);
         const int ncols = 1 << sp.lm_c, nrows = 1 << sp.lm_r;
-        int citems = 0;
-        for (int r0 = 0; r0 < ncols; r0 += cu, ++citems) {
+        for (int r0 = 0; r0 < ncols; r0 += cu) {
             HostBatchItem it{};
             it.cfg = sp.ccfg;
             it.nunits = std::min(cu, ncols - r0);
             it.first = r0;
             it.log_m = sp.lm_c;
-            it.wait_slot = -1;
-            it.post_slot = slot;
+            it.phase = 0;
+            it.slot = slot;
             it.in_off = off[t];
             it.out_off = ws_elems;
-            cols.push_back(it);
+            items.push_back(it);
         }
         for (int q0 = 0; q0 < nrows; q0 += ru) {
             HostBatchItem it{};
@@ -133,9 +131,8 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
             it.nunits = std::min(ru, nrows - q0);
             it.first = q0;
             it.log_m = sp.lm_r;
-            it.wait_slot = slot;
-            it.wait_need = citems;
-            it.post_slot = -1;
+            it.phase = 1;
+            it.slot = slot;
             it.in_off = ws_elems;
             it.out_off = off[t];
             rows.push_back(it);
@@ -153,23 +150,23 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
             it.cfg = cfg;
             it.nunits = (int)std::min<size_t>(upw, v.size() - i);
             it.first = (int)offs.size();
-            it.wait_slot = -1;
-            it.post_slot = -1;
+            it.phase = 0;
+            it.slot = -1;
             for (int k = 0; k < it.nunits; ++k) offs.push_back(v[i + k]);
-            small.push_back(it);
+            items.push_back(it);
         }
     }
-    items = cols;
-    items.insert(items.end(), small.begin(), small.end());
+    phase0 = (int64_t)items.size();
     items.insert(items.end(), rows.begin(), rows.end());
-    nslots = slot;
 }
 
-static void build_items(fft_batch* b) {
+static int build_items(fft_batch* b) {
+    if (batch_resident_grid(b->dtype, b->device, &b->resident) != FFT_OK) return FFT_EHIP;
     int64_t ws_elems = 0;
     build_work(b->n.data(), b->offset.data(), b->count, b->cfg_choice, b->items, b->offs, ws_elems,
-               b->nslots);
+               b->phase0);
     b->ws_bytes = (size_t)ws_elems * elem_bytes(b->dtype);
+    return FFT_OK;
 }
 
 // Resident workgroups of the persistent kernel (its grid when the work list is
@@ -193,10 +190,9 @@ static int upload(fft_batch* b) {
     if (b->ws) { (void)hipFree(b->ws); b->ws = nullptr; }
     const size_t ib = std::max<size_t>(1, b->items.size()) * sizeof(HostBatchItem);
     const size_t ob = std::max<size_t>(1, b->offs.size()) * sizeof(int64_t);
-    b->ctl_words = 2 + b->nslots;
     if ((e = hipMalloc(&b->d_items, ib)) != hipSuccess) return hip_error(e, "hipMalloc(items)");
     if ((e = hipMalloc(&b->d_offs, ob)) != hipSuccess) return hip_error(e, "hipMalloc(offsets)");
-    if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * b->ctl_words)) != hipSuccess)
+    if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * 2)) != hipSuccess)
         return hip_error(e, "hipMalloc(control)");
     if (b->ws_bytes && (e = hipMalloc(&b->ws, b->ws_bytes)) != hipSuccess)
         return e == hipErrorOutOfMemory ? set_error(FFT_ENOMEM, "batch workspace allocation failed")
@@ -209,78 +205,91 @@ static int upload(fft_batch* b) {
         (e = hipMemcpy(b->d_offs, b->offs.data(), b->offs.size() * sizeof(int64_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_error(e, "hipMemcpy(offsets)");
-    if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * b->ctl_words)) != hipSuccess)
-        return hip_error(e, "hipMemset(control)");
-    int resident = 0;
-    if (batch_resident_grid(b->dtype, b->device, &resident) != FFT_OK) return FFT_EHIP;
-    b->grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)b->items.size(), resident));
+    if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * 2)) != hipSuccess)
+        return hip_error(e, "hipMemset(queue heads)");
+    const int64_t n1 = (int64_t)b->items.size() - b->phase0;
+    b->grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(b->phase0, b->resident));
+    b->grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, b->resident));
+    b->grid = std::max(b->grid0, b->grid1);
     return FFT_OK;
 }
 
-static void drop_graph(fft_batch* b) {
-    if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
-    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
-    b->knode = nullptr;
-    b->cap_in = nullptr;
-    b->cap_out = nullptr;
+// Kernel-node arguments of one phase; the pointers in `slots` must outlive
+// the hipGraphAddKernelNode / hipGraphExecKernelNodeSetParams call.
+struct PhaseArgs {
+    const void* in;
+    void* out;
+    void* ws;
+    const void* lt;
+    const void* items;
+    const int64_t* offs;
+    int first, nitems;
+    unsigned* head;
+    void* slots[9];
+    PhaseArgs(const fft_batch* b, const void* in_, void* out_, int phase)
+        : in(in_), out(out_), ws(b->ws), lt(b->table->ptr), items(b->d_items), offs(b->d_offs),
+          first(phase == 0 ? 0 : (int)b->phase0),
+          nitems(phase == 0 ? (int)b->phase0 : (int)((int64_t)b->items.size() - b->phase0)),
+          head(b->d_ctl + phase) {
+        void* p[9] = {&in, &out, &ws, &lt, &items, &offs, &first, &nitems, &head};
+        std::copy(p, p + 9, slots);
+    }
+};
+
+static hipKernelNodeParams phase_params(const fft_batch* b, PhaseArgs& a, int phase) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(batch_kernel_func(b->dtype));
+    kp.gridDim = dim3(phase == 0 ? b->grid0 : b->grid1);
+    kp.blockDim = dim3(kHostBatchThreads);
+    kp.sharedMemBytes = (unsigned)batch_lds_bytes(b->dtype);
+    kp.kernelParams = a.slots;
+    kp.extra = nullptr;
+    return kp;
 }
 
-// Captures reset + persistent kernel once on the plan's own stream.
-static int capture(fft_batch* b, const void* in, void* out) {
+// Builds the graph once: queue-head reset, phase 0, phase 1 (each a
+// persistent kernel), in that order.
+static int build_graph(fft_batch* b, const void* in, void* out) {
     hipError_t e;
-    if (!b->cap_stream && (e = hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking)) != hipSuccess)
-        return hip_error(e, "hipStreamCreate");
-    if ((e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-        return hip_error(e, "hipStreamBeginCapture");
-    hipError_t le = launch_batch_reset(b->d_ctl, b->ctl_words, b->cap_stream);
-    hipError_t lk = hipSuccess;
-    if (le == hipSuccess)
-        lk = launch_batch(b->dtype, in, out, b->ws, b->table->ptr, b->d_items, b->d_offs,
-                          (int)b->items.size(), b->d_ctl, kSpinLimit, b->grid, b->cap_stream);
-    hipGraph_t g = nullptr;
-    e = hipStreamEndCapture(b->cap_stream, &g);
-    if (le != hipSuccess) return hip_error(le, "capture(reset)");
-    if (lk != hipSuccess) return hip_error(lk, "capture(batch kernel)");
-    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
-    b->graph = g;
-    size_t nn = 0;
-    if ((e = hipGraphGetNodes(g, nullptr, &nn)) != hipSuccess) return hip_error(e, "hipGraphGetNodes");
-    std::vector<hipGraphNode_t> nodes(nn);
-    if ((e = hipGraphGetNodes(g, nodes.data(), &nn)) != hipSuccess) return hip_error(e, "hipGraphGetNodes");
-    for (auto nd : nodes) {
-        hipGraphNodeType ty;
-        if (hipGraphNodeGetType(nd, &ty) != hipSuccess || ty != hipGraphNodeTypeKernel) continue;
-        hipKernelNodeParams kp;
-        if (hipGraphKernelNodeGetParams(nd, &kp) != hipSuccess) continue;
-        if (kp.func == batch_kernel_func(b->dtype)) b->knode = nd;
+    if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_error(e, "hipGraphCreate");
+    unsigned* ctl = b->d_ctl;
+    int nheads = 2;
+    void* rargs[] = {&ctl, &nheads};
+    hipKernelNodeParams rp{};
+    rp.func = const_cast<void*>(batch_reset_func());
+    rp.gridDim = dim3(1);
+    rp.blockDim = dim3(64);
+    rp.sharedMemBytes = 0;
+    rp.kernelParams = rargs;
+    rp.extra = nullptr;
+    hipGraphNode_t reset = nullptr;
+    if ((e = hipGraphAddKernelNode(&reset, b->graph, nullptr, 0, &rp)) != hipSuccess)
+        return hip_error(e, "hipGraphAddKernelNode(reset)");
+    hipGraphNode_t prev = reset;
+    for (int ph = 0; ph < 2; ++ph) {
+        PhaseArgs a(b, in, out, ph);
+        if (a.nitems == 0) continue;
+        hipKernelNodeParams kp = phase_params(b, a, ph);
+        if ((e = hipGraphAddKernelNode(&b->knode[ph], b->graph, &prev, 1, &kp)) != hipSuccess)
+            return hip_error(e, "hipGraphAddKernelNode(phase)");
+        prev = b->knode[ph];
     }
-    if (!b->knode) return set_error(FFT_EHIP, "batch kernel node not found in the captured graph");
-    if ((e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0)) != hipSuccess)
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
         return hip_error(e, "hipGraphInstantiate");
     b->cap_in = in;
     b->cap_out = out;
     return FFT_OK;
 }
 
-// Points the captured kernel node at new data buffers.
+// Points both phase nodes at new data buffers.
 static int retarget(fft_batch* b, const void* in, void* out) {
-    hipKernelNodeParams kp;
-    hipError_t e = hipGraphKernelNodeGetParams(b->knode, &kp);
-    if (e != hipSuccess) return hip_error(e, "hipGraphKernelNodeGetParams");
-    const void* a_in = in;
-    void* a_out = out;
-    void* a_ws = b->ws;
-    const void* a_lt = b->table->ptr;
-    const void* a_items = b->d_items;
-    const int64_t* a_offs = b->d_offs;
-    int a_n = (int)b->items.size();
-    unsigned* a_ctl = b->d_ctl;
-    int a_spin = kSpinLimit;
-    void* args[] = {&a_in, &a_out, &a_ws, &a_lt, &a_items, &a_offs, &a_n, &a_ctl, &a_spin};
-    kp.kernelParams = args;
-    kp.extra = nullptr;
-    if ((e = hipGraphExecKernelNodeSetParams(b->exec, b->knode, &kp)) != hipSuccess)
-        return hip_error(e, "hipGraphExecKernelNodeSetParams");
+    for (int ph = 0; ph < 2; ++ph) {
+        if (!b->knode[ph]) continue;
+        PhaseArgs a(b, in, out, ph);
+        hipKernelNodeParams kp = phase_params(b, a, ph);
+        hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->knode[ph], &kp);
+        if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams");
+    }
     b->cap_in = in;
     b->cap_out = out;
     return FFT_OK;
@@ -298,7 +307,7 @@ int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s) {
         return set_error(FFT_EINVAL, "in and out partially overlap");
     if (b->items.empty()) return FFT_OK;
     int rc = FFT_OK;
-    if (!b->exec) rc = capture(b, in, out);
+    if (!b->exec) rc = build_graph(b, in, out);
     else if (b->cap_in != in || b->cap_out != out) rc = retarget(b, in, out);
     if (rc != FFT_OK) return rc;
     hipError_t e = hipGraphLaunch(b->exec, s);
@@ -347,7 +356,7 @@ fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, co
         return nullptr;
     }
     if (get_table(nmax, dtype, kind, &b->table) != FFT_OK) return nullptr;
-    build_items(b.get());
+    if (build_items(b.get()) != FFT_OK) return nullptr;
     if (upload(b.get()) != FFT_OK) return nullptr;
     if ((e = hipEventCreateWithFlags(&b->last, hipEventDisableTiming)) != hipSuccess) {
         hip_error(e, "hipEventCreate");
@@ -383,17 +392,6 @@ int fft_batch_elements(const fft_batch* b, int64_t* elements) {
     return FFT_OK;
 }
 
-int fft_batch_status(fft_batch* b, int* flags) {
-    if (!b || !flags) return set_error(FFT_EINVAL, "null argument");
-    hipError_t e = hipEventSynchronize(b->last);
-    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
-    unsigned f = 0;
-    if ((e = hipMemcpy(&f, b->d_ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_error(e, "hipMemcpy(status)");
-    *flags = (int)f;
-    return FFT_OK;
-}
-
 int fft_batch_info(const fft_batch* b, int64_t* items, int64_t* grid, size_t* workspace_bytes) {
     if (!b) return set_error(FFT_EINVAL, "null batch");
     if (items) *items = (int64_t)b->items.size();
@@ -403,5 +401,37 @@ int fft_batch_info(const fft_batch* b, int64_t* items, int64_t* grid, size_t* wo
 }
 
 void fft_batch_destroy(fft_batch* b) { delete b; }
+
+int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int64_t item_cap,
+                        int64_t* nitems, int64_t* phase0, int64_t* offs_out, int64_t offs_cap,
+                        int64_t* noffs, int64_t* ws_elems) {
+    if (!n || count < 0 || !nitems || !phase0 || !noffs || !ws_elems)
+        return set_error(FFT_EINVAL, "null argument");
+    std::vector<int64_t> sizes(n, n + count), offset(count);
+    int64_t total = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const int64_t v = n[i];
+        if (v < 2 || (v & (v - 1)) || v > (int64_t(1) << 18))
+            return set_error(FFT_EINVAL, "batch sizes must be powers of two in [2, 2^18]");
+        offset[i] = total;
+        total += v;
+    }
+    std::vector<HostBatchItem> items;
+    std::vector<int64_t> offs;
+    build_work(sizes.data(), offset.data(), count, kSmallCfg, items, offs, *ws_elems, *phase0);
+    *nitems = (int64_t)items.size();
+    *noffs = (int64_t)offs.size();
+    if (!items_out && !offs_out) return FFT_OK;     // size query
+    if ((int64_t)items.size() > item_cap || (int64_t)offs.size() > offs_cap)
+        return set_error(FFT_EINVAL, "output capacity too small (sizes returned in nitems, noffs)");
+    for (size_t i = 0; i < items.size(); ++i) {
+        const HostBatchItem& it = items[i];
+        const int64_t row[8] = {it.cfg, it.nunits, it.first, it.log_m, it.phase, it.slot,
+                                it.in_off, it.out_off};
+        std::copy(row, row + 8, items_out + 8 * i);
+    }
+    std::copy(offs.begin(), offs.end(), offs_out);
+    return FFT_OK;
+}
 
 }  // extern "C"

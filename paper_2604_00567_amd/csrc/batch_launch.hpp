@@ -10,11 +10,12 @@
 
 namespace dsfft {
 
-// Mirrors BatchItem in fft_batch.hpp (checked by a static_assert there).
+// Work item of the uneven-batch kernel (fields described in fft_batch.hpp).
 struct HostBatchItem {
-    int32_t cfg, nunits, first, log_m, wait_slot, wait_need, post_slot, reserved;
+    int32_t cfg, nunits, first, log_m, phase, slot, reserved0, reserved1;
     int64_t in_off, out_off;
 };
+static_assert(sizeof(HostBatchItem) == 48, "work item layout");
 
 // Configuration ids (same order as BatchCfg in fft_batch.hpp).
 enum HostBatchCfg {
@@ -26,22 +27,30 @@ enum HostBatchCfg {
 };
 
 constexpr int kHostBatchThreads = 256;
-constexpr int kSpinLimit = 1 << 22;    // dependency-wait sleeps (~512 cycles each): about a second
 
 extern const int kSmallCfg[14];        // single-unit configuration per log2 N (1..13)
 int cfg_upw(int cfg);                  // units per workgroup of a configuration
 
-// Work list for transforms of sizes n[t] at element offsets off[t] (batch.cpp).
+// Work list for transforms of sizes n[t] at element offsets off[t] (batch.cpp):
+// phase-0 items (column items, then single-unit items) come first, `phase0`
+// of them, then the phase-1 row items.
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
                 std::vector<HostBatchItem>& items, std::vector<int64_t>& offs, int64_t& ws_elems,
-                int& nslots);
+                int64_t& phase0);
 int batch_resident_grid(int dtype, int device, int* out);
 
 size_t batch_lds_bytes(int dtype);
 const void* batch_kernel_func(int dtype);
+const void* batch_reset_func();
 hipError_t launch_batch_reset(unsigned* ctl, int n, hipStream_t s);
+// One phase: items first .. first + nitems - 1, queue head *head.
 hipError_t launch_batch(int dtype, const void* in, void* out, void* ws, const void* lt,
-                        const void* items, const int64_t* offs, int nitems, unsigned* ctl,
-                        int spin_limit, int grid, hipStream_t s);
+                        const void* items, const int64_t* offs, int first, int nitems,
+                        unsigned* head, int grid, hipStream_t s);
+// Both phases of a work list (reset of the two queue heads ctl[0..1], then
+// phase 0 and phase 1) on stream s.
+hipError_t launch_batch_phases(int dtype, const void* in, void* out, void* ws, const void* lt,
+                               const void* items, const int64_t* offs, int phase0, int nitems,
+                               unsigned* ctl, int grid0, int grid1, hipStream_t s);
 
 }  // namespace dsfft

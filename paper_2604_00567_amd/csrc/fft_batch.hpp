@@ -1,17 +1,19 @@
-// Uneven-size batch: one persistent, work-queue kernel runs transforms of many
-// sizes in a single launch.  Work items are claimed in order with an atomic
-// counter; each item is one workgroup's worth of units of one size class and
-// runs the same register-pass / LDS-exchange code as the regular kernels.
+// Uneven-size batch: persistent, work-queue kernels run transforms of many
+// sizes.  Work items are claimed in order with an atomic counter; each item
+// is one workgroup's worth of units of one size class and runs the same
+// register-pass / LDS-exchange code as the regular kernels.
 //
 // Transforms up to 2^13 points are single-unit items (whole transforms).
-// Larger ones (2^14 .. 2^18) use the two-kernel split of the global schedule
-// inside the same launch: column items (stages 1..log2 N1, into a workspace)
-// and row items (the remaining stages, into the output).  A row item waits on
-// a per-transform counter until all column items of its transform are done;
-// every column item is queued before every row item, so the items a row item
-// waits for have already been claimed by running workgroups and the wait ends.
-// The wait is bounded (spin_limit sleeps); on expiry the kernel records an
-// error flag and carries on, so every wave always reaches the end.
+// Larger ones (2^14 .. 2^18) use the two-kernel split of the global schedule:
+// column items (stages 1..log2 N1, into a workspace) and row items (the
+// remaining stages, into the output).  The work list has two phases, each
+// run by one launch of the persistent kernel: phase 0 = every column item,
+// then the single-unit items; phase 1 = every row item.  The launch boundary
+// is what makes the column results visible to the row items.  (Inside one
+// launch, a row item would have to wait on counters with agent-scope
+// acquire/release: on a part with one L2 per XCD each such release writes
+// back and each acquire invalidates the whole L2 of its XCD, which cost far
+// more than a second launch.)
 #pragma once
 
 #include "batch_launch.hpp"
@@ -28,9 +30,8 @@ constexpr int kBatchMaxElems = 32;     // elements per lane, largest configurati
 //   first      single-unit items: first index into the offset list;
 //              column/row items: first residue / row
 //   log_m      column/row items: log2(N / NU)
-//   wait_slot  row items: counter to wait on, else -1
-//   wait_need  row items: column items of the transform
-//   post_slot  column items: counter to increment when done, else -1
+//   phase      0 (columns, single-unit) or 1 (rows)
+//   slot       column/row items: index of the large transform, else -1
 //   in_off     column items: transform start in the input; row items: in the workspace
 //   out_off    column items: transform start in the workspace; row items: in the output
 using BatchItem = HostBatchItem;
@@ -39,6 +40,7 @@ using BatchItem = HostBatchItem;
 struct BatchGeo {
     const int64_t* offs;
     BatchItem it;
+    int lane_id;       // threadIdx.x, made opaque per configuration (batch_unit)
     template <int LOG_NU, int MODE>
     __device__ __forceinline__ UnitGeom get(int ul) const {
         UnitGeom u;
@@ -64,16 +66,24 @@ struct BatchGeo {
         return u;
     }
     __device__ __forceinline__ bool active(int ul) const { return ul < it.nunits; }
+    __device__ __forceinline__ int tid() const { return lane_id; }
     __device__ __forceinline__ int64_t block_first(int) const { return 0; }
     __device__ __forceinline__ int64_t block_units(int) const { return 0; }
 };
 
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
-__device__ __forceinline__ void batch_unit(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
+__device__ __forceinline__ void batch_unit(E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                            const E* src, E* dst, const BatchGeo& geo) {
     static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 256 threads");
     static_assert((1 << LOG_E) <= kBatchMaxElems, "too many elements per lane");
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, geo);
+    E v[1 << LOG_E];   // per configuration, so each case keeps its own registers
+    // The thread index is read through an empty asm statement in each case:
+    // index arithmetic common to several cases then cannot be hoisted above
+    // the dispatch, where it would stay live in every case.
+    BatchGeo g = geo;
+    g.lane_id = (int)threadIdx.x;
+    asm volatile("" : "+v"(g.lane_id));
+    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, g);
 }
 
 // Largest LDS footprint over the batch configurations, in elements.
@@ -94,83 +104,66 @@ constexpr int batch_lds_elems() {
 }
 
 template <class E>
-__device__ __forceinline__ void batch_dispatch(int cfg, E* v, E* lds,
+__device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
                                                const typename TwOf<E>::type* __restrict__ lt,
                                                const E* in, E* out, E* ws, const BatchGeo& g) {
     switch (cfg) {
-        case HB_N2: batch_unit<E, 1, 1, 256, MODE_SMALL, 1, 0, 0>(v, lds, lt, in, out, g); break;
-        case HB_N4: batch_unit<E, 2, 2, 256, MODE_SMALL, 2, 0, 0>(v, lds, lt, in, out, g); break;
-        case HB_N8: batch_unit<E, 3, 3, 256, MODE_SMALL, 3, 0, 0>(v, lds, lt, in, out, g); break;
-        case HB_N16: batch_unit<E, 4, 2, 64, MODE_SMALL, 2, 2, 0>(v, lds, lt, in, out, g); break;
-        case HB_N32: batch_unit<E, 5, 3, 64, MODE_SMALL, 3, 2, 0>(v, lds, lt, in, out, g); break;
-        case HB_N64: batch_unit<E, 6, 3, 32, MODE_SMALL, 3, 3, 0>(v, lds, lt, in, out, g); break;
-        case HB_N128: batch_unit<E, 7, 4, 32, MODE_SMALL, 4, 3, 0>(v, lds, lt, in, out, g); break;
-        case HB_N256: batch_unit<E, 8, 4, 16, MODE_SMALL, 4, 4, 0>(v, lds, lt, in, out, g); break;
-        case HB_N512: batch_unit<E, 9, 5, 16, MODE_SMALL, 5, 4, 0>(v, lds, lt, in, out, g); break;
-        case HB_N1024: batch_unit<E, 10, 5, 8, MODE_SMALL, 5, 5, 0>(v, lds, lt, in, out, g); break;
-        case HB_N2048: batch_unit<E, 11, 5, 4, MODE_SMALL, 5, 3, 3>(v, lds, lt, in, out, g); break;
-        case HB_N4096: batch_unit<E, 12, 4, 1, MODE_SMALL, 4, 4, 4>(v, lds, lt, in, out, g); break;
-        case HB_N8192: batch_unit<E, 13, 5, 1, MODE_SMALL, 5, 4, 4>(v, lds, lt, in, out, g); break;
-        case HB_N1024_B: batch_unit<E, 10, 4, 4, MODE_SMALL, 4, 3, 3>(v, lds, lt, in, out, g); break;
-        case HB_N4096_B: batch_unit<E, 12, 5, 2, MODE_SMALL, 5, 4, 3>(v, lds, lt, in, out, g); break;
-        case HB_COLS128: batch_unit<E, 7, 4, 32, MODE_COLS, 4, 3, 0>(v, lds, lt, in, ws, g); break;
-        case HB_ROWS128: batch_unit<E, 7, 4, 32, MODE_ROWS, 4, 3, 0>(v, lds, lt, ws, out, g); break;
-        case HB_COLS256: batch_unit<E, 8, 4, 16, MODE_COLS, 4, 4, 0>(v, lds, lt, in, ws, g); break;
-        case HB_ROWS256: batch_unit<E, 8, 4, 16, MODE_ROWS, 4, 4, 0>(v, lds, lt, ws, out, g); break;
-        case HB_COLS512: batch_unit<E, 9, 5, 16, MODE_COLS, 5, 4, 0>(v, lds, lt, in, ws, g); break;
-        case HB_ROWS512: batch_unit<E, 9, 5, 16, MODE_ROWS, 5, 4, 0>(v, lds, lt, ws, out, g); break;
+        case HB_N2: batch_unit<E, 1, 1, 256, MODE_SMALL, 1, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N4: batch_unit<E, 2, 2, 256, MODE_SMALL, 2, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N8: batch_unit<E, 3, 3, 256, MODE_SMALL, 3, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N16: batch_unit<E, 4, 2, 64, MODE_SMALL, 2, 2, 0>(lds, lt, in, out, g); break;
+        case HB_N32: batch_unit<E, 5, 3, 64, MODE_SMALL, 3, 2, 0>(lds, lt, in, out, g); break;
+        case HB_N64: batch_unit<E, 6, 3, 32, MODE_SMALL, 3, 3, 0>(lds, lt, in, out, g); break;
+        case HB_N128: batch_unit<E, 7, 4, 32, MODE_SMALL, 4, 3, 0>(lds, lt, in, out, g); break;
+        case HB_N256: batch_unit<E, 8, 4, 16, MODE_SMALL, 4, 4, 0>(lds, lt, in, out, g); break;
+        case HB_N512: batch_unit<E, 9, 5, 16, MODE_SMALL, 5, 4, 0>(lds, lt, in, out, g); break;
+        case HB_N1024: batch_unit<E, 10, 5, 8, MODE_SMALL, 5, 5, 0>(lds, lt, in, out, g); break;
+        case HB_N2048: batch_unit<E, 11, 5, 4, MODE_SMALL, 5, 3, 3>(lds, lt, in, out, g); break;
+        case HB_N4096: batch_unit<E, 12, 4, 1, MODE_SMALL, 4, 4, 4>(lds, lt, in, out, g); break;
+        case HB_N8192: batch_unit<E, 13, 5, 1, MODE_SMALL, 5, 4, 4>(lds, lt, in, out, g); break;
+        case HB_N1024_B: batch_unit<E, 10, 4, 4, MODE_SMALL, 4, 3, 3>(lds, lt, in, out, g); break;
+        case HB_N4096_B: batch_unit<E, 12, 5, 2, MODE_SMALL, 5, 4, 3>(lds, lt, in, out, g); break;
+        case HB_COLS128: batch_unit<E, 7, 4, 32, MODE_COLS, 4, 3, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS128: batch_unit<E, 7, 4, 32, MODE_ROWS, 4, 3, 0>(lds, lt, ws, out, g); break;
+        case HB_COLS256: batch_unit<E, 8, 4, 16, MODE_COLS, 4, 4, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS256: batch_unit<E, 8, 4, 16, MODE_ROWS, 4, 4, 0>(lds, lt, ws, out, g); break;
+        case HB_COLS512: batch_unit<E, 9, 5, 16, MODE_COLS, 5, 4, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS512: batch_unit<E, 9, 5, 16, MODE_ROWS, 5, 4, 0>(lds, lt, ws, out, g); break;
         default: break;
     }
 }
 
-// ctl[0]: queue head, ctl[1]: error flag, ctl[2 + s]: column items finished for
-// big transform s.  The control block is cleared by batch_reset_kernel before
-// each launch.
+// Items first .. first + nitems - 1 of one phase; *head is the phase's queue
+// head (zero at launch).
 template <class E>
-__global__ void __launch_bounds__(kBatchThreads)
+__global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(sizeof(E) == 4 ? 4 : 2)))
 fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __restrict__ lt,
                  const BatchItem* __restrict__ items, const int64_t* __restrict__ offs,
-                 int nitems, unsigned* ctl, int spin_limit) {
+                 int first, int nitems, unsigned* head) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     __shared__ int s_item;
-    E v[kBatchMaxElems];
     for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(&ctl[0], 1u);
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
         __syncthreads();
-        const int idx = s_item;
+        // the item index is uniform: in scalar registers, the item's fields
+        // and the addresses derived from them stay scalar too
+        const int idx = __builtin_amdgcn_readfirstlane(s_item);
         __syncthreads();
         if (idx >= nitems) break;
-        const BatchItem it = items[idx];
-        if (it.wait_slot >= 0) {
-            if (threadIdx.x == 0) {
-                int spins = 0;
-                while (__hip_atomic_load(&ctl[2 + it.wait_slot], __ATOMIC_ACQUIRE,
-                                         __HIP_MEMORY_SCOPE_AGENT) < (unsigned)it.wait_need) {
-                    if (++spins > spin_limit) {
-                        atomicOr(&ctl[1], 1u);
-                        break;
-                    }
-                    __builtin_amdgcn_s_sleep(8);
-                }
-            }
-            __syncthreads();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        const BatchGeo geo{offs, it};
-        batch_dispatch<E>(it.cfg, v, lds, lt, in, out, ws, geo);
-        if (it.post_slot >= 0) {
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (threadIdx.x == 0)
-                __hip_atomic_fetch_add(&ctl[2 + it.post_slot], 1u, __ATOMIC_RELEASE,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-        }
+        const BatchItem it = items[first + idx];
+        const BatchGeo geo{offs, it, 0};
+        // An opaque copy of the table pointer per item keeps each case's
+        // twiddle address arithmetic inside the loop; hoisted out of it, the
+        // addresses of every case would stay live across the whole loop.
+        const typename TwOf<E>::type* lt_item = lt;
+        asm volatile("" : "+s"(lt_item));
+        batch_dispatch<E>(it.cfg, lds, lt_item, in, out, ws, geo);
         __syncthreads();   // the item's LDS is consumed before the next item reuses it
     }
 }
 
-// Clears the control block (a kernel rather than a memset node, so the graph
+// Clears the queue heads (a kernel rather than a memset node, so the graph
 // holds kernels only).
 __global__ void batch_reset_kernel(unsigned* ctl, int n) {
     for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) ctl[i] = 0u;

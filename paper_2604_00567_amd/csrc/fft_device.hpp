@@ -308,11 +308,13 @@ __device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __
 struct GridGeo {
     int64_t ublk, units;
     int log_m;
+    int lane_id;       // threadIdx.x (opaque per block in the persistent loop)
     template <int LOG_NU, int MODE>
     __device__ __forceinline__ UnitGeom get(int ul) const {
         return unit_geom<LOG_NU, MODE>(ublk + ul, log_m);
     }
     __device__ __forceinline__ bool active(int ul) const { return ublk + ul < units; }
+    __device__ __forceinline__ int tid() const { return lane_id; }
     // staging: the workgroup's units are elements [first, first + count)
     __device__ __forceinline__ int64_t block_first(int log_nu) const { return ublk << log_nu; }
     __device__ __forceinline__ int64_t block_units(int upw) const {
@@ -334,7 +336,7 @@ __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
     constexpr int M = 1 << PP::log_m(0);
     constexpr int GPL = EL / R;
     constexpr bool unit_fast = (MODE == MODE_COLS);
-    const int tid = threadIdx.x;
+    const int tid = gp.tid();
     const int ul = unit_fast ? (tid % UPW) : (tid / G);
     const int g = unit_fast ? (tid / UPW) : (tid % G);
     if (gp.active(ul)) {
@@ -377,7 +379,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr int GPL = EL / R;
         constexpr int NT_OF = UPW * G;
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
-        const int tid = threadIdx.x;
+        const int tid = gp.tid();
         const int ul = unit_fast ? (tid % UPW) : (tid / G);
         const int g0 = unit_fast ? (tid / UPW) : (tid % G);
         // lane-tail units: the last pass takes group (r, q) on lane q + 16 r
@@ -561,28 +563,36 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
         const int64_t nblk = (units + UPW - 1) / UPW;
         const int64_t step = gridDim.x;
         int64_t blk = blockIdx.x;
+        // The thread index is re-read through an empty asm statement for each
+        // block, so index arithmetic is recomputed per block instead of being
+        // hoisted out of the loop and held in registers throughout it.
+        auto geo = [&](int64_t b) {
+            int t = (int)threadIdx.x;
+            asm volatile("" : "+v"(t));
+            return GridGeo{b * UPW, units, log_m, t};
+        };
         if (blk < nblk)
             load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
-                v, in, GridGeo{blk * UPW, units, log_m});
+                v, in, geo(blk));
         while (blk < nblk) {
             if (blk + step < nblk)
                 load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
-                    vb, in, GridGeo{(blk + step) * UPW, units, log_m});
+                    vb, in, geo(blk + step));
             unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
-                v, lds, lt, in, out, GridGeo{blk * UPW, units, log_m});
+                v, lds, lt, in, out, geo(blk));
             __syncthreads();    // LDS is reused by the next block
             blk += step;
             if (blk >= nblk) break;
             if (blk + step < nblk)
                 load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
-                    v, in, GridGeo{(blk + step) * UPW, units, log_m});
+                    v, in, geo(blk + step));
             unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
-                vb, lds, lt, in, out, GridGeo{blk * UPW, units, log_m});
+                vb, lds, lt, in, out, geo(blk));
             __syncthreads();
             blk += step;
         }
     } else {
-        const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m};
+        const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

@@ -75,7 +75,7 @@ fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int6
     if (get_table(int64_t(1) << 18, s->dtype, s->kind, &s->table) != FFT_OK) return nullptr;
     if ((e = hipMalloc(&s->d_items, sizeof(HostBatchItem) * max_items)) != hipSuccess ||
         (e = hipMalloc(&s->d_offs, sizeof(int64_t) * max_transforms)) != hipSuccess ||
-        (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * (2 + max_large))) != hipSuccess ||
+        (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * 2)) != hipSuccess ||
         (ws_bytes && (e = hipMalloc(&s->ws, ws_bytes)) != hipSuccess) ||
         (e = hipHostMalloc((void**)&s->h_items, sizeof(HostBatchItem) * max_items, 0)) != hipSuccess ||
         (e = hipHostMalloc((void**)&s->h_offs, sizeof(int64_t) * max_transforms, 0)) != hipSuccess) {
@@ -105,6 +105,7 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
         return hip_error(e, "hipEventSynchronize");
     s->tn.clear();
     s->toff.clear();
+    int64_t nlarge = 0;
     for (int64_t r = 0; r < nreq; ++r) {
         const int64_t v = n[r];
         if (v < 2 || (v & (v - 1)) || v > (int64_t(1) << 18) || batch[r] < 1 || off[r] < 0)
@@ -113,13 +114,13 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
             s->tn.push_back(v);
             s->toff.push_back(off[r] + j * v);
         }
+        if (v >= (int64_t(1) << 14)) nlarge += batch[r];
     }
-    int64_t ws_elems = 0;
-    int nslots = 0;
-    build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice, s->items, s->offs,
-               ws_elems, nslots);
+    int64_t ws_elems = 0, phase0 = 0;
+    build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice, s->items,
+               s->offs, ws_elems, phase0);
     if ((int64_t)s->items.size() > s->item_cap || (int64_t)s->offs.size() > s->offs_cap ||
-        nslots > s->slot_cap || (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
+        nlarge > s->slot_cap || (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
         return set_error(FFT_ENOMEM, "step exceeds the slot's capacity");
     if (s->items.empty()) return FFT_OK;
     std::copy(s->items.begin(), s->items.end(), s->h_items);
@@ -131,11 +132,12 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
         (e = hipMemcpyAsync(s->d_offs, s->h_offs, sizeof(int64_t) * s->offs.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
         return hip_error(e, "hipMemcpyAsync(offsets)");
-    if ((e = launch_batch_reset(s->d_ctl, 2 + nslots, st)) != hipSuccess)
-        return hip_error(e, "launch(reset)");
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((int64_t)s->items.size(), s->resident));
-    if ((e = launch_batch(s->dtype, data, data, s->ws, s->table->ptr, s->d_items, s->d_offs,
-                          (int)s->items.size(), s->d_ctl, kSpinLimit, grid, st)) != hipSuccess)
+    const int64_t n1 = (int64_t)s->items.size() - phase0;
+    const int grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(phase0, s->resident));
+    const int grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, s->resident));
+    if ((e = launch_batch_phases(s->dtype, data, data, s->ws, s->table->ptr, s->d_items, s->d_offs,
+                                 (int)phase0, (int)s->items.size(), s->d_ctl, grid0, grid1, st)) !=
+        hipSuccess)
         return hip_error(e, "launch(batch)");
     if ((e = hipEventRecord(s->done, st)) != hipSuccess) return hip_error(e, "hipEventRecord");
     s->launched = true;
@@ -150,21 +152,6 @@ int fft_serve_slot_query(fft_serve_slot* s) {
     if (e == hipSuccess) return 1;
     if (e == hipErrorNotReady) return 0;
     return hip_error(e, "hipEventQuery");
-}
-
-// Status flags of the slot's last launch after waiting for it (bit 0: a
-// bounded dependency wait expired).
-int fft_serve_slot_status(fft_serve_slot* s, int* flags) {
-    if (!s || !flags) return set_error(FFT_EINVAL, "null argument");
-    *flags = 0;
-    if (!s->launched) return FFT_OK;
-    hipError_t e = hipEventSynchronize(s->done);
-    if (e != hipSuccess) return hip_error(e, "hipEventSynchronize");
-    unsigned f = 0;
-    if ((e = hipMemcpy(&f, s->d_ctl + 1, sizeof(unsigned), hipMemcpyDeviceToHost)) != hipSuccess)
-        return hip_error(e, "hipMemcpy(status)");
-    *flags = (int)f;
-    return FFT_OK;
 }
 
 void fft_serve_slot_destroy(fft_serve_slot* s) { delete s; }

@@ -179,9 +179,6 @@ class Server:
             with torch.cuda.stream(slot.stream):
                 for rid, (dt, off, n, b) in slot.placement.items():
                     self.outputs[rid] = slot.arena[dt][off * 2:(off + n * b) * 2].clone()
-        for dt, h in slot.native.items():
-            if binding.fft_serve_slot_status(h) != 0:
-                raise RuntimeError("a dependency wait expired inside a serving step")
         slot.busy = False
         slot.rids = []
 

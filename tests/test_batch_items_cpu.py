@@ -1,64 +1,121 @@
-"""CPU model of the uneven-batch work list (mirrors batch.cpp's ordering rule)
-checking the properties the persistent kernel relies on: every element is
-covered exactly once, workspace slices are disjoint, and every row item only
-waits on column items queued before it."""
+"""The uneven-batch work list as the library builds it (fft_batch_work_list,
+host only), checked for what the two persistent kernels rely on: every
+element of every transform is covered exactly once, workspace slices are
+disjoint, and every row item is in the second phase while every column item
+is in the first."""
 import numpy as np
+import pytest
 
-from paper_2604_00567_amd import inputs
+from paper_2604_00567_amd import binding, inputs
 
-UPW_SMALL = {1: 256, 2: 256, 3: 256, 4: 64, 5: 64, 6: 32, 7: 32, 8: 16, 9: 16, 10: 8, 11: 4,
-             12: 1, 13: 1}
-SPLIT = {14: (7, 32, 7, 32, 7), 15: (8, 16, 7, 32, 8), 16: (8, 16, 8, 16, 8)}  # (lognu_c, upw_c, lognu_r, upw_r, ...)
-
-
-def build(sizes):
-    cols, rows, small = [], [], []
-    ws, slot, offset = 0, 0, 0
-    offs = []
-    by_class = {}
-    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]])
-    for t, n in enumerate(sizes):
-        m = int(n).bit_length() - 1
-        if m <= 13:
-            by_class.setdefault(m, []).append(int(starts[t]))
-            continue
-        lnc, uc, lnr, ur, _ = SPLIT[m]
-        lm_c, lm_r = m - lnc, m - lnr
-        citems = 0
-        for r0 in range(0, 1 << lm_c, uc):
-            cols.append(("c", t, r0, min(uc, (1 << lm_c) - r0), slot, ws))
-            citems += 1
-        for q0 in range(0, 1 << lm_r, ur):
-            rows.append(("r", t, q0, min(ur, (1 << lm_r) - q0), slot, citems, ws))
-        ws += int(n)
-        slot += 1
-    for m in sorted(by_class, reverse=True):
-        v = by_class[m]
-        for i in range(0, len(v), UPW_SMALL[m]):
-            small.append(("s", m, len(offs), min(UPW_SMALL[m], len(v) - i)))
-            offs.extend(v[i:i + UPW_SMALL[m]])
-    return cols + small + rows, offs, ws
+F = {k: i for i, k in enumerate(binding.WORK_FIELDS)}
+# units per item and log2 NU of each configuration id (order of HostBatchCfg)
+CFG_LOGNU = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 10, 12, 7, 7, 8, 8, 9, 9]
 
 
-def test_work_list_properties():
-    sizes = inputs.uneven_sizes(4096, seed=4, log_lo=1, log_hi=16)
-    items, offs, ws = build(sizes)
-    # single-unit transforms appear exactly once
-    small_starts = sorted(offs)
-    expect = sorted(int(s) for s, n in zip(np.concatenate([[0], np.cumsum(sizes)[:-1]]), sizes)
-                    if n <= 1 << 13)
-    assert small_starts == expect
-    # every residue / row of a big transform exactly once; waits point backwards
-    seen_cols, done_cols = {}, {}
+def classify(it):
+    if it[F["phase"]] == 1:
+        return "row"
+    if it[F["slot"]] >= 0:
+        return "col"
+    return "small"
+
+
+def check(sizes):
+    sizes = np.asarray(sizes, np.int64)
+    items, phase0, offs, ws = binding.fft_batch_work_list(sizes)
+    assert np.all(items[:phase0, F["phase"]] == 0) and np.all(items[phase0:, F["phase"]] == 1)
+    starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    large = sizes >= (1 << 14)
+    assert ws == int(sizes[large].sum())
+
+    # single-unit transforms: each start exactly once, with the class's config
+    small_starts = []
+    for it in items:
+        if classify(it) == "small":
+            ln = CFG_LOGNU[it[F["cfg"]]]
+            for k in range(it[F["nunits"]]):
+                o = int(offs[it[F["first"]] + k])
+                small_starts.append(o)
+                t = int(np.searchsorted(starts, o))
+                assert starts[t] == o and sizes[t] == 1 << ln
+    assert sorted(small_starts) == sorted(int(s) for s in starts[~large])
+
+    # large transforms: columns and rows each covered once; waits point back
+    by_slot = {}
+    ws_slices = {}
+    last_col = {}
     for pos, it in enumerate(items):
-        if it[0] == "c":
-            _, t, r0, nu, slot, w = it
-            seen_cols.setdefault(t, set()).update(range(r0, r0 + nu))
-            done_cols[slot] = done_cols.get(slot, 0) + 1
-        elif it[0] == "r":
-            _, t, q0, nu, slot, need, w = it
-            assert done_cols.get(slot, 0) == need, "row item queued before its column items"
-    for t, s in seen_cols.items():
+        kind = classify(it)
+        if kind == "col":
+            s = it[F["slot"]]
+            t = int(np.searchsorted(starts, it[F["in_off"]]))
+            assert starts[t] == it[F["in_off"]] and large[t]
+            m = int(sizes[t]).bit_length() - 1
+            ln = CFG_LOGNU[it[F["cfg"]]]
+            assert it[F["log_m"]] == m - ln
+            by_slot.setdefault(s, {"t": t, "cols": [], "rows": []})
+            assert by_slot[s]["t"] == t
+            by_slot[s]["cols"].extend(range(it[F["first"]], it[F["first"]] + it[F["nunits"]]))
+            ws_slices.setdefault(s, it[F["out_off"]])
+            assert ws_slices[s] == it[F["out_off"]]
+            last_col[s] = pos
+        elif kind == "row":
+            s = it[F["slot"]]
+            assert s in last_col, "row item ahead of its transform's column items"
+            assert it[F["in_off"]] == ws_slices[s]
+            t = by_slot[s]["t"]
+            assert it[F["out_off"]] == starts[t]
+            m = int(sizes[t]).bit_length() - 1
+            assert it[F["log_m"]] == m - CFG_LOGNU[it[F["cfg"]]]
+            by_slot[s]["rows"].extend(range(it[F["first"]], it[F["first"]] + it[F["nunits"]]))
+            by_slot[s].setdefault("first_row", pos)
+            by_slot[s]["nrows"] = 1 << int(it[F["log_m"]])
+    for s, d in by_slot.items():
+        t = d["t"]
         m = int(sizes[t]).bit_length() - 1
-        assert s == set(range(1 << (m - SPLIT[m][0])))
-    assert ws == int(np.sum(sizes[sizes > (1 << 13)]))
+        ncols = 1 << (m - CFG_LOGNU[items[last_col[s]][F["cfg"]]])
+        assert sorted(d["cols"]) == list(range(ncols))
+        assert sorted(d["rows"]) == list(range(d["nrows"]))
+        # the two kernels split the stages: columns x rows points = N
+        lc = CFG_LOGNU[items[last_col[s]][F["cfg"]]]
+        assert (1 << lc) * ncols == sizes[t] and d["nrows"] * ncols >= 1
+    # workspace slices are disjoint and tile [0, ws)
+    sl = sorted((ws_slices[s], int(sizes[by_slot[s]["t"]])) for s in by_slot)
+    pos = 0
+    for a, n in sl:
+        assert a == pos
+        pos += n
+    assert pos == ws
+    return items, by_slot, last_col
+
+
+def test_work_list_mixed_sizes():
+    sizes = inputs.uneven_sizes(4096, seed=4, log_lo=1, log_hi=18)
+    check(sizes)
+
+
+def test_work_list_order():
+    sizes = inputs.uneven_sizes(600, seed=7, log_lo=6, log_hi=17)
+    items, _, _ = check(sizes)
+    kinds = [classify(it) for it in items]
+    # columns, then whole transforms (largest first), then rows
+    order = [k for i, k in enumerate(kinds) if i == 0 or k != kinds[i - 1]]
+    assert order == ["col", "small", "row"]
+    small_lognu = [CFG_LOGNU[it[F["cfg"]]] for it in items if classify(it) == "small"]
+    assert small_lognu == sorted(small_lognu, reverse=True)
+
+
+def test_work_list_only_small_or_only_large():
+    items, phase0, offs, ws = binding.fft_batch_work_list([64] * 100)
+    assert phase0 == len(items) and ws == 0 and len(offs) == 100
+    items, phase0, offs, ws = binding.fft_batch_work_list([1 << 16] * 3)
+    assert 0 < phase0 < len(items) and ws == 3 << 16 and len(offs) == 0
+    check([1 << 16] * 3)
+
+
+def test_work_list_rejects_bad_sizes():
+    with pytest.raises(binding.FFTError):
+        binding.fft_batch_work_list([1024, 3])
+    with pytest.raises(binding.FFTError):
+        binding.fft_batch_work_list([1 << 19])

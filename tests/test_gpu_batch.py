@@ -29,7 +29,6 @@ def run_batch(sizes, x, dtype, replays=1, choice=None, inplace=False):
         for r in range(replays):
             b.execute(xt, yt)
             torch.cuda.synchronize()
-            assert b.status() == 0
             outs.append(yt.cpu().numpy().copy())
             # eager work between replays, on the same stream
             z = torch.randn(1 << 20, device="cuda:0")
@@ -76,7 +75,6 @@ def test_graph_replays_and_new_buffers():
             dst.zero_()
             b.execute(src, dst)
             torch.cuda.synchronize()
-            assert b.status() == 0
             res.append(dst.cpu().numpy().copy())
             torch.randn(4096, device="cuda:0").sum().item()   # eager work in between
         assert mismatches(res[0], res[2]) == 0 and mismatches(res[1], res[3]) == 0
