@@ -51,10 +51,30 @@ def rotating_sets(torch, x0: np.ndarray, min_bytes: float = 1.2e9):
     return xs, ys
 
 
+SETTLE_S = 0.05
+
+
+def settle(torch, run, nsets: int, seconds: float = SETTLE_S):
+    """Runs the step untimed for `seconds` of wall time: after an idle spell
+    (host-side input generation) the device needs tens of milliseconds of
+    load before its clocks are back at their working level, and the first
+    launches after it run several percent slower."""
+    t0 = time.perf_counter()
+    i = 0
+    while time.perf_counter() - t0 < seconds:
+        run(i % nsets)
+        i += 1
+        if i % 16 == 0:
+            torch.cuda.synchronize()
+    torch.cuda.synchronize()
+
+
 def timed_loop(torch, run, nsets: int, steps: int, warmup: int):
     """Times `steps` calls of run(i) between one pair of HIP events on the
-    current stream (the stream the library launches on), after `warmup`
-    untimed calls; wall time is taken between device synchronisations."""
+    current stream (the stream the library launches on), after the settle
+    phase and `warmup` untimed calls; wall time is taken between device
+    synchronisations."""
+    settle(torch, run, nsets)
     for i in range(warmup):
         run(i % nsets)
     torch.cuda.synchronize()
@@ -329,6 +349,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": round(ms, 4),
         "higher_is_better": True,
+        "settle_s": SETTLE_S,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f16",

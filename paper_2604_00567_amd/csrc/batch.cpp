@@ -20,18 +20,17 @@ const int kSmallCfg[14] = {-1, HB_N2, HB_N4, HB_N8, HB_N16, HB_N32, HB_N64, HB_N
                                   HB_N256, HB_N512, HB_N1024, HB_N2048, HB_N4096, HB_N8192};
 int cfg_upw(int cfg) {
     switch (cfg) {
-        case HB_N2: case HB_N4: case HB_N8: return 256;
-        case HB_N16: case HB_N32: return 64;
-        case HB_N64: case HB_N128: case HB_COLS128: case HB_ROWS128: return 32;
-        case HB_N256: case HB_N512: case HB_COLS256: case HB_ROWS256: case HB_COLS512:
-        case HB_ROWS512: return 16;
-        case HB_N1024: return 8;
-        case HB_N2048: case HB_N1024_B: return 4;
-        case HB_N4096_B: return 2;
-        default: return 1;       // HB_N4096, HB_N8192
+        case HB_N2: case HB_N4: case HB_N8: return 512;
+        case HB_N16: case HB_N32: return 128;
+        case HB_N64: case HB_N128: case HB_COLS128: case HB_ROWS128: case HB_COLS256:
+        case HB_ROWS256: return 64;
+        case HB_N256: case HB_N512: case HB_COLS512: case HB_ROWS512: return 32;
+        case HB_N1024: return 16;
+        case HB_N2048: case HB_N1024_B: return 8;
+        case HB_N4096_B: return 4;
+        default: return 2;       // HB_N4096, HB_N8192
     }
 }
-
 
 }  // namespace dsfft
 

@@ -26,7 +26,7 @@ enum HostBatchCfg {
     HB_COUNT
 };
 
-constexpr int kHostBatchThreads = 256;
+constexpr int kHostBatchThreads = 512;
 
 extern const int kSmallCfg[14];        // single-unit configuration per log2 N (1..13)
 int cfg_upw(int cfg);                  // units per workgroup of a configuration

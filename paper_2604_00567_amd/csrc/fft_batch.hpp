@@ -74,7 +74,7 @@ struct BatchGeo {
 template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
 __device__ __forceinline__ void batch_unit(E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                            const E* src, E* dst, const BatchGeo& geo) {
-    static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 256 threads");
+    static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 512 threads");
     static_assert((1 << LOG_E) <= kBatchMaxElems, "too many elements per lane");
     E v[1 << LOG_E];   // per configuration, so each case keeps its own registers
     // The thread index is read through an empty asm statement in each case:
@@ -90,15 +90,15 @@ __device__ __forceinline__ void batch_unit(E* lds, const typename TwOf<E>::type*
 constexpr int batch_lds_elems() {
     int m = 0;
     const int sizes[] = {
-        256 * PassPlan<1, 1, 0, 0>::region(), 256 * PassPlan<2, 2, 0, 0>::region(),
-        256 * PassPlan<3, 3, 0, 0>::region(), 64 * PassPlan<4, 2, 2, 0>::region(),
-        64 * PassPlan<5, 3, 2, 0>::region(), 32 * PassPlan<6, 3, 3, 0>::region(),
-        32 * PassPlan<7, 4, 3, 0>::region(), 16 * PassPlan<8, 4, 4, 0>::region(),
-        16 * PassPlan<9, 5, 4, 0>::region(), 8 * PassPlan<10, 5, 5, 0>::region(),
-        4 * PassPlan<11, 5, 3, 3>::region(), 1 * PassPlan<12, 4, 4, 4>::region(),
-        1 * PassPlan<13, 5, 4, 4>::region(), 4 * PassPlan<10, 4, 3, 3>::region(),
-        2 * PassPlan<12, 5, 4, 3>::region(), 32 * PassPlan<7, 4, 3, 0>::region(),
-        16 * PassPlan<8, 4, 4, 0>::region(), 16 * PassPlan<9, 5, 4, 0>::region()};
+        512 * PassPlan<1, 1, 0, 0>::region(), 512 * PassPlan<2, 2, 0, 0>::region(),
+        512 * PassPlan<3, 3, 0, 0>::region(), 128 * PassPlan<4, 2, 2, 0>::region(),
+        128 * PassPlan<5, 3, 2, 0>::region(), 64 * PassPlan<6, 3, 3, 0>::region(),
+        64 * PassPlan<7, 4, 3, 0>::region(), 32 * PassPlan<8, 4, 4, 0>::region(),
+        32 * PassPlan<9, 5, 4, 0>::region(), 16 * PassPlan<10, 5, 5, 0>::region(),
+        8 * PassPlan<11, 5, 3, 3>::region(), 2 * PassPlan<12, 4, 4, 4>::region(),
+        2 * PassPlan<13, 5, 4, 4>::region(), 8 * PassPlan<10, 4, 3, 3>::region(),
+        4 * PassPlan<12, 5, 4, 3>::region(), 64 * PassPlan<7, 4, 3, 0>::region(),
+        64 * PassPlan<8, 5, 3, 0>::region(), 32 * PassPlan<9, 5, 4, 0>::region()};
     for (int s : sizes) m = s > m ? s : m;
     return m;
 }
@@ -108,27 +108,27 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
                                                const typename TwOf<E>::type* __restrict__ lt,
                                                const E* in, E* out, E* ws, const BatchGeo& g) {
     switch (cfg) {
-        case HB_N2: batch_unit<E, 1, 1, 256, MODE_SMALL, 1, 0, 0>(lds, lt, in, out, g); break;
-        case HB_N4: batch_unit<E, 2, 2, 256, MODE_SMALL, 2, 0, 0>(lds, lt, in, out, g); break;
-        case HB_N8: batch_unit<E, 3, 3, 256, MODE_SMALL, 3, 0, 0>(lds, lt, in, out, g); break;
-        case HB_N16: batch_unit<E, 4, 2, 64, MODE_SMALL, 2, 2, 0>(lds, lt, in, out, g); break;
-        case HB_N32: batch_unit<E, 5, 3, 64, MODE_SMALL, 3, 2, 0>(lds, lt, in, out, g); break;
-        case HB_N64: batch_unit<E, 6, 3, 32, MODE_SMALL, 3, 3, 0>(lds, lt, in, out, g); break;
-        case HB_N128: batch_unit<E, 7, 4, 32, MODE_SMALL, 4, 3, 0>(lds, lt, in, out, g); break;
-        case HB_N256: batch_unit<E, 8, 4, 16, MODE_SMALL, 4, 4, 0>(lds, lt, in, out, g); break;
-        case HB_N512: batch_unit<E, 9, 5, 16, MODE_SMALL, 5, 4, 0>(lds, lt, in, out, g); break;
-        case HB_N1024: batch_unit<E, 10, 5, 8, MODE_SMALL, 5, 5, 0>(lds, lt, in, out, g); break;
-        case HB_N2048: batch_unit<E, 11, 5, 4, MODE_SMALL, 5, 3, 3>(lds, lt, in, out, g); break;
-        case HB_N4096: batch_unit<E, 12, 4, 1, MODE_SMALL, 4, 4, 4>(lds, lt, in, out, g); break;
-        case HB_N8192: batch_unit<E, 13, 5, 1, MODE_SMALL, 5, 4, 4>(lds, lt, in, out, g); break;
-        case HB_N1024_B: batch_unit<E, 10, 4, 4, MODE_SMALL, 4, 3, 3>(lds, lt, in, out, g); break;
-        case HB_N4096_B: batch_unit<E, 12, 5, 2, MODE_SMALL, 5, 4, 3>(lds, lt, in, out, g); break;
-        case HB_COLS128: batch_unit<E, 7, 4, 32, MODE_COLS, 4, 3, 0>(lds, lt, in, ws, g); break;
-        case HB_ROWS128: batch_unit<E, 7, 4, 32, MODE_ROWS, 4, 3, 0>(lds, lt, ws, out, g); break;
-        case HB_COLS256: batch_unit<E, 8, 4, 16, MODE_COLS, 4, 4, 0>(lds, lt, in, ws, g); break;
-        case HB_ROWS256: batch_unit<E, 8, 4, 16, MODE_ROWS, 4, 4, 0>(lds, lt, ws, out, g); break;
-        case HB_COLS512: batch_unit<E, 9, 5, 16, MODE_COLS, 5, 4, 0>(lds, lt, in, ws, g); break;
-        case HB_ROWS512: batch_unit<E, 9, 5, 16, MODE_ROWS, 5, 4, 0>(lds, lt, ws, out, g); break;
+        case HB_N2: batch_unit<E, 1, 1, 512, MODE_SMALL, 1, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N4: batch_unit<E, 2, 2, 512, MODE_SMALL, 2, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N8: batch_unit<E, 3, 3, 512, MODE_SMALL, 3, 0, 0>(lds, lt, in, out, g); break;
+        case HB_N16: batch_unit<E, 4, 2, 128, MODE_SMALL, 2, 2, 0>(lds, lt, in, out, g); break;
+        case HB_N32: batch_unit<E, 5, 3, 128, MODE_SMALL, 3, 2, 0>(lds, lt, in, out, g); break;
+        case HB_N64: batch_unit<E, 6, 3, 64, MODE_SMALL, 3, 3, 0>(lds, lt, in, out, g); break;
+        case HB_N128: batch_unit<E, 7, 4, 64, MODE_SMALL, 4, 3, 0>(lds, lt, in, out, g); break;
+        case HB_N256: batch_unit<E, 8, 4, 32, MODE_SMALL, 4, 4, 0>(lds, lt, in, out, g); break;
+        case HB_N512: batch_unit<E, 9, 5, 32, MODE_SMALL, 5, 4, 0>(lds, lt, in, out, g); break;
+        case HB_N1024: batch_unit<E, 10, 5, 16, MODE_SMALL, 5, 5, 0>(lds, lt, in, out, g); break;
+        case HB_N2048: batch_unit<E, 11, 5, 8, MODE_SMALL, 5, 3, 3>(lds, lt, in, out, g); break;
+        case HB_N4096: batch_unit<E, 12, 4, 2, MODE_SMALL, 4, 4, 4>(lds, lt, in, out, g); break;
+        case HB_N8192: batch_unit<E, 13, 5, 2, MODE_SMALL, 5, 4, 4>(lds, lt, in, out, g); break;
+        case HB_N1024_B: batch_unit<E, 10, 4, 8, MODE_SMALL, 4, 3, 3>(lds, lt, in, out, g); break;
+        case HB_N4096_B: batch_unit<E, 12, 5, 4, MODE_SMALL, 5, 4, 3>(lds, lt, in, out, g); break;
+        case HB_COLS128: batch_unit<E, 7, 4, 64, MODE_COLS, 4, 3, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS128: batch_unit<E, 7, 4, 64, MODE_ROWS, 4, 3, 0>(lds, lt, ws, out, g); break;
+        case HB_COLS256: batch_unit<E, 8, 5, 64, MODE_COLS, 5, 3, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS256: batch_unit<E, 8, 5, 64, MODE_ROWS, 5, 3, 0>(lds, lt, ws, out, g); break;
+        case HB_COLS512: batch_unit<E, 9, 5, 32, MODE_COLS, 5, 4, 0>(lds, lt, in, ws, g); break;
+        case HB_ROWS512: batch_unit<E, 9, 5, 32, MODE_ROWS, 5, 4, 0>(lds, lt, ws, out, g); break;
         default: break;
     }
 }
@@ -142,15 +142,21 @@ fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __res
                  int first, int nitems, unsigned* head) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
-    __shared__ int s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(head, 1u);
-        __syncthreads();
-        // the item index is uniform: in scalar registers, the item's fields
-        // and the addresses derived from them stay scalar too
-        const int idx = __builtin_amdgcn_readfirstlane(s_item);
-        __syncthreads();
-        if (idx >= nitems) break;
+    // Claims run one item ahead: the claim of the next item is issued when
+    // the current one starts, so its round trip overlaps the current item's
+    // work, and published in LDS when the item ends.  Two slots alternate:
+    // the slot written at the end of item k was last read after the barrier
+    // that ended item k - 2, and every thread has since passed the barrier
+    // that ended item k - 1.
+    __shared__ int s_item[2];
+    if (threadIdx.x == 0) s_item[0] = (int)atomicAdd(head, 1u);
+    __syncthreads();
+    // the item index is uniform: in scalar registers, the item's fields and
+    // the addresses derived from them stay scalar too
+    int idx = __builtin_amdgcn_readfirstlane(s_item[0]);
+    for (int k = 1; idx < nitems; ++k) {
+        // the returned index is needed only at the end of the item
+        const unsigned next = threadIdx.x == 0 ? atomicAdd(head, 1u) : 0u;
         const BatchItem it = items[first + idx];
         const BatchGeo geo{offs, it, 0};
         // An opaque copy of the table pointer per item keeps each case's
@@ -159,7 +165,9 @@ fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __res
         const typename TwOf<E>::type* lt_item = lt;
         asm volatile("" : "+s"(lt_item));
         batch_dispatch<E>(it.cfg, lds, lt_item, in, out, ws, geo);
-        __syncthreads();   // the item's LDS is consumed before the next item reuses it
+        if (threadIdx.x == 0) s_item[k & 1] = (int)next;
+        __syncthreads();   // LDS consumed before the next item reuses it; next claim visible
+        idx = __builtin_amdgcn_readfirstlane(s_item[k & 1]);
     }
 }
 

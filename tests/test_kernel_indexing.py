@@ -309,3 +309,55 @@ def test_two_pass_index_math(m1, m2):
     assert np.all(w2 == 1)
     ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
     assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+BATCH_SRC = os.path.join(os.path.dirname(os.path.dirname(__file__)),
+                         "paper_2604_00567_amd", "csrc", "fft_batch.hpp")
+
+
+def load_batch_configs():
+    """The uneven-batch kernel's configurations, as (name, config tuple)."""
+    out = {}
+    for line in open(BATCH_SRC):
+        m = re.match(r"\s*case (HB_\w+): batch_unit<E, (\d+), (\d+), (\d+), (\w+), (\d+), (\d+), "
+                     r"(\d+)>", line)
+        if m:
+            lognu, loge, upw = int(m.group(2)), int(m.group(3)), int(m.group(4))
+            lrs = tuple(int(m.group(i)) for i in (6, 7, 8))
+            out[m.group(1)] = (MODES[m.group(5)], lognu, loge, upw) + lrs + (0, 0)
+    return out
+
+
+def test_batch_configs_parsed():
+    cfgs = load_batch_configs()
+    assert len(cfgs) == 21
+    for name, c in cfgs.items():
+        assert c[3] << (c[1] - c[2]) == 512, name       # every configuration uses 512 threads
+        assert sum(c[4:7]) == c[1], name
+
+
+@pytest.mark.parametrize("name", [n for n, c in load_batch_configs().items() if c[0] == 0])
+def test_batch_small_configs_index_math(name):
+    cfg = load_batch_configs()[name]
+    n = 1 << cfg[1]
+    batch = cfg[3] + 1
+    x, out, written, _ = simulate(cfg, n, batch)
+    assert np.all(written == 1)
+    ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+@pytest.mark.parametrize("cols,rows", [("HB_COLS128", "HB_ROWS128"), ("HB_COLS256", "HB_ROWS128"),
+                                       ("HB_COLS256", "HB_ROWS256"), ("HB_COLS512", "HB_ROWS256"),
+                                       ("HB_COLS512", "HB_ROWS512")])
+def test_batch_two_pass_index_math(cols, rows):
+    cfgs = load_batch_configs()
+    c, r = cfgs[cols], cfgs[rows]
+    n = 1 << (c[1] + r[1])
+    batch = 1
+    x, ws, w1, _ = simulate(c, n, batch)
+    assert np.all(w1 == 1)
+    _, out, w2, _ = simulate(r, n, batch, x=ws)
+    assert np.all(w2 == 1)
+    ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n
