@@ -125,8 +125,9 @@ std::string describe(const KernelCfg* k) {
     return buf;
 }
 
-// Largest single-kernel size per dtype, and the two-pass split.
-static int small_limit(int dtype) { return dtype == DT_F16 ? 14 : 14; }
+// Largest single-kernel size per dtype (a binary16 transform of 2^15 points,
+// 128 KiB, still fits one workgroup's LDS), and the two-pass split.
+static int small_limit(int dtype) { return dtype == DT_F16 ? 15 : 14; }
 
 int choose_schedule(fft_plan* p, const int* variants) {
     const int m = p->log_n;

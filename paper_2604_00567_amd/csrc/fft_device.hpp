@@ -391,9 +391,10 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 
         // ---- gather
         if constexpr (P == 0 && STG) {
-            // The workgroup's units are contiguous in memory: copy the block
-            // into LDS (natural order) with 16-byte streaming loads, then
-            // gather the pass's decimated groups from LDS.
+            // The workgroup's units are contiguous in memory (whole transforms,
+            // or consecutive rows of the workspace): copy the block into LDS
+            // (natural order) with 16-byte streaming loads, then gather the
+            // pass's decimated groups from LDS.
             stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, gp.block_first(LOG_NU),
                                               gp.block_units(UPW) << LOG_NU);
             const E* nat = lds + ul * NU;
@@ -478,8 +479,9 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 for (int e = 0; e < R; ++e) reg[r + (M + PAD) * (q + L0 * e)] = v[u * R + e];
             }
             __syncthreads();
-        } else if constexpr (STG) {
+        } else if constexpr (STG && MODE == MODE_SMALL) {
             // outputs to LDS in natural order, then 16-byte streaming stores
+            // (row units stage only their input: their outputs are strided)
             __syncthreads();                      // every lane is done reading LDS
             E* nat = lds + ul * NU;
 #pragma unroll
@@ -549,7 +551,7 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
     static_assert(LR0 + LR1 + LR2 + 2 * LANE == LOG_NU, "radices must multiply to NU");
     static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
     static_assert(MODE != MODE_ROWS || LR1 > 0, "row units need two passes");
-    static_assert(STG == 0 || MODE == MODE_SMALL, "staging needs contiguous units");
+    static_assert(STG == 0 || MODE != MODE_COLS, "staging needs contiguous units");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE == 0 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");

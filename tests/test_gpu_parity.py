@@ -74,16 +74,20 @@ def test_every_table_kind_n1024(dtype, kind):
 
 
 @pytest.mark.parametrize("dtype", ["f16", "f32"])
-@pytest.mark.parametrize("n", [256, 1024, 2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("n", [256, 1024, 2048, 4096, 8192, 16384, 1 << 15, 1 << 16, 1 << 18, 1 << 20])
 def test_every_compiled_configuration(dtype, n):
+    """Every single-kernel configuration, and every column x row pair of the
+    two-pass schedule, bit for bit against the oracle."""
     single, cols, rows = binding.fft_config_count(n, dtype)
-    x = inputs.uniform(n, 9, 7, dtype)
+    batch = max(2, min(9, (1 << 18) // n))
+    x = inputs.uniform(n, batch, 7, dtype)
     ref = oracle.emulate(x, "dual_select", dtype)
     for v in range(single):
         assert mismatches(run_gpu(x, dtype, "dual_select", variant=(v, 0, False)), ref) == 0, v
-    if cols and rows:
-        y = run_gpu(x, dtype, "dual_select", variant=(0, 0, True))
-        assert mismatches(y, ref) == 0
+    for a in range(cols):
+        for b in range(rows):
+            y = run_gpu(x, dtype, "dual_select", variant=(a, b, True))
+            assert mismatches(y, ref) == 0, (a, b)
 
 
 @pytest.mark.parametrize("dtype", ["f16", "f32"])

@@ -169,7 +169,9 @@ def simulate(cfg, n, batch, x=None):
                     gam = g + G * u
                     if p == 0 and stg:
                         # staged: the block sits in LDS in natural order
-                        assert mode == 0 and EL * 4 >= 16
+                        # (whole transforms, or consecutive workspace rows)
+                        assert mode in (0, 2) and EL * 4 >= 16
+                        assert base_in == unit << log_nu
                         r = gam
                         for i in range(R):
                             idx = r + M * i
@@ -295,11 +297,12 @@ def test_persistent_blocks_cover_once():
             assert sorted(seen) == list(range(nblk))
 
 
-@pytest.mark.parametrize("m1,m2", [(6, 6), (7, 6), (7, 7), (8, 6)])
-def test_two_pass_index_math(m1, m2):
+@pytest.mark.parametrize("m1,m2,rows_staged", [(6, 6, 0), (7, 6, 0), (7, 7, 0), (8, 6, 0), (7, 7, 1),
+                                                (8, 7, 1), (8, 8, 1)])
+def test_two_pass_index_math(m1, m2, rows_staged):
     cfgs = load_configs()
     cols = next(c for c in cfgs if c[0] == 1 and c[1] == m1)
-    rows = next(c for c in cfgs if c[0] == 2 and c[1] == m2)
+    rows = next(c for c in cfgs if c[0] == 2 and c[1] == m2 and c[7] == rows_staged)
     assert cols[-1] == 0 and rows[-1] == 0
     n = 1 << (m1 + m2)
     batch = 2
