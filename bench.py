@@ -8,11 +8,13 @@ so the 256 MB memory-side cache cannot serve repeated inputs.  Algorithmic
 bytes per transform: 2 * N * 4 (one read, one write of binary16 pairs); the
 twiddle table is excluded.
 
-Reported beside it (not the headline value): N = 4096 x 16384; the large-N
-sweep N = 2^10..2^20 with batch * N = 2^26 (binary16 and binary32); the
-binary32 single-size case N = 1024 x 16 with all table kinds; the uneven
-batch of 4096 transforms with N = 2^U, U uniform over 6..16, in one graph
-replay of the persistent kernel, against one plan per size class; the serving
+Reported beside it (not the headline value): the same kernel with each table
+kind; the inverse transform at the headline size and the forward -> inverse
+round trip per table kind; N = 4096 x 16384; the large-N sweep N = 2^10..2^20
+with batch * N = 2^26 (binary16 and binary32); the binary32 single-size case
+N = 1024 x 16 with all table kinds; the uneven batch of 4096 transforms with
+N = 2^U, U uniform over 6..16, in one graph replay (two persistent kernels),
+against one plan per size class; the serving
 loop on Poisson arrivals at 20k requests/s against one launch per request;
 and the CPU oracle on the host cores.  Prints one JSON line.
 """
@@ -234,7 +236,7 @@ def bench_uneven(torch, binding, inputs, steps, warmup):
             "pct_hbm_peak": 100 * algo / wall / 1e9 / HBM_PEAK_GBS,
             "items": info["items"], "grid": info["grid"],
             "per_class_plans_gbs": algo / wall_c / 1e9, "per_class_launches": len(plans),
-            "form": "one HIP-graph replay of the persistent kernel per step"}
+            "form": "one HIP-graph replay per step (reset, two persistent kernels)"}
 
 
 def bench_sweep(torch, binding, inputs, steps):
@@ -252,6 +254,31 @@ def bench_sweep(torch, binding, inputs, steps):
                         "rel_l2": e["rel_l2"], "config": r["config"]})
             del x0, y
             torch.cuda.empty_cache()
+    return out
+
+
+def bench_round_trip(torch, binding, inputs):
+    """x -> forward -> inverse on the GPU, divided by N, against x: relative L2
+    per table kind and precision (Sec. V quotes about 1e-7 in binary32),
+    N = 1024 x 16, re/im N(0, 1)."""
+    out = {}
+    for dt in ("f32", "f16"):
+        x = inputs.normal(1024, 16, 1, dt)
+        xt = torch.from_numpy(x).to("cuda:0")
+        for kind in ("dual_select", "linzer_feig", "cosine", "lf_w0_exempt"):
+            f = binding.Plan(1024, 16, dt, kind)
+            b = binding.Plan(1024, 16, dt, kind, direction="inverse")
+            yt, zt = torch.empty_like(xt), torch.empty_like(xt)
+            f.execute(xt, yt)
+            b.execute(yt, zt)
+            torch.cuda.synchronize()
+            f.close()
+            b.close()
+            z = zt.cpu().numpy().astype(np.float64) / 1024
+            bad = int(np.count_nonzero(~np.isfinite(z)))
+            xd = x.astype(np.float64)
+            out[f"{dt}_{kind}"] = {"rel_l2": None if bad else float(np.linalg.norm(z - xd) / np.linalg.norm(xd)),
+                                   "nonfinite": bad}
     return out
 
 
@@ -377,9 +404,17 @@ def main():
         lf["dual_select_vs_lf_w0_exempt_max_abs_ratio"] = (
             lf["lf_w0_exempt"]["max_abs"] / ds_max if ds_max else None)
         result["comparison_tables"] = lf
-        log("same kernel, each table kind")
+        log("same kernel, each table kind; inverse")
         result["table_kind_timing"] = time_kinds(torch, binding, bufs["xs"], bufs["ys"], 1024, 65536,
                                                  "f16", args.steps, args.warmup)
+        inv = binding.Plan(1024, 65536, "f16", "dual_select", direction="inverse")
+        xs_, ys_ = bufs["xs"], bufs["ys"]
+        _, dev = timed_loop(torch, lambda i: inv.execute(xs_[i], ys_[i]), len(xs_), args.steps,
+                            args.warmup)
+        inv.close()
+        result["inverse_n1024"] = {"kernel_ms": round(dev * 1e3, 4),
+                                   "gbs": round(2.0 * 1024 * 65536 * 4 / dev / 1e9, 1)}
+        result["round_trip"] = bench_round_trip(torch, binding, inputs)
         del yout
         log("timing N=4096 x 16384 f16 dual-select")
         sec, x02, y2 = time_plan(torch, binding, inputs, 4096, 16384, "f16", "dual_select",

@@ -60,6 +60,16 @@ typedef enum {
     FFT_TABLE_LF_W0_EXEMPT = 3
 } fft_table_kind;
 
+/* Transform direction, as the sign of the exponent: FFT_FORWARD computes
+ * X[k] = sum_n x[n] exp(-j 2 pi n k / N) (eq. (1)); FFT_INVERSE computes
+ * x[n] = sum_k X[k] exp(+j 2 pi n k / N), unnormalised (a round trip returns
+ * N times the input).  The inverse uses the same butterflies and kernels with
+ * the table built by the same rules from the conjugate twiddles W^{-k}: on
+ * the cosine path (mult, ratio) becomes (mult, -ratio), on the sine path
+ * (-mult, -ratio).  The paper uses the inverse only for its round-trip error
+ * (Sec. V); which inverse it uses is not stated, this one is the reading. */
+enum { FFT_FORWARD = -1, FFT_INVERSE = 1 };
+
 typedef struct fft_plan fft_plan;     /* opaque; immutable after creation   */
 typedef struct fft_batch fft_batch;   /* opaque uneven-size batch plan      */
 typedef struct fft_serve_slot fft_serve_slot;   /* one in-flight serving launch */
@@ -79,8 +89,14 @@ const char* fft_last_error(void);
  */
 fft_plan* fft_plan_create(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind);
 
+/* Same, in the given direction (FFT_FORWARD or FFT_INVERSE; anything else is
+ * FFT_EINVAL).  fft_plan_create(...) is fft_plan_create_dir(..., FFT_FORWARD). */
+fft_plan* fft_plan_create_dir(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                              int direction);
+
 /*
- * Enqueues the batched forward FFT out = FFT(in) on `stream` and returns
+ * Enqueues the plan's batched transform (forward FFT, or the inverse for a
+ * plan made with FFT_INVERSE) out = FFT(in) on `stream` and returns
  * without synchronising.  in/out: device pointers of batch*n elements each.
  * A plan must not run concurrently on two streams (its workspace is shared).
  * Returns FFT_OK, FFT_EINVAL (null plan/pointer, misalignment, partial overlap)
@@ -103,6 +119,10 @@ void fft_destroy(fft_plan* plan);
  */
 int fft_table_build(int64_t n, fft_dtype dtype, fft_table_kind kind,
                     void* mult_out, void* ratio_out, uint8_t* path_out);
+
+/* Same for a direction (FFT_FORWARD or FFT_INVERSE). */
+int fft_table_build_dir(int64_t n, fft_dtype dtype, fft_table_kind kind, int direction,
+                        void* mult_out, void* ratio_out, uint8_t* path_out);
 
 /* The plan's parameters and its kernel choice, for tests and reports.
  * config_out receives a NUL-terminated description (up to `cap` bytes). */

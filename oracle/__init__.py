@@ -7,9 +7,10 @@ and its Python binding never import it, and the two share no code.
 It wraps ``oracle_core.c`` (plain C, FP64, OpenMP over the batch), built with
 gcc into ``oracle/_liboracle.so``:
 
-* ``table(n, kind)``: FP64 twiddle table -- Algorithm 1 (dual-select), the
-  epsilon-clamped Linzer-Feig table of Sec. II-B, the cosine table of Sec. II-C,
-  and Linzer-Feig with W^0 exempted;
+* ``table(n, kind, inverse)``: FP64 twiddle table -- Algorithm 1 (dual-select),
+  the epsilon-clamped Linzer-Feig table of Sec. II-B, the cosine table of
+  Sec. II-C, and Linzer-Feig with W^0 exempted; ``inverse=True`` applies the
+  same rules to the conjugate twiddles W^{-k} (the inverse transform);
 * ``dft64`` (eq. (1) written out), ``fft64`` (radix-2 Stockham, 10-flop butterfly
   of eqs. (std1)-(std2));
 * ``emulate_f16`` / ``emulate_f32`` / ``emulate_f64``: the radix-2 Stockham pass
@@ -60,12 +61,12 @@ def _load():
     lib = ctypes.CDLL(_LIB)
     i64, i32, dp = ctypes.c_int64, ctypes.c_int, ctypes.c_void_p
     for name, args in {
-        "orc_table": [i64, i32, dp, dp, dp],
-        "orc_fft64": [i64, i64, dp, dp],
-        "orc_dft64": [i64, i64, dp, dp],
-        "orc_emulate_f64": [i64, i64, i32, dp, dp],
-        "orc_emulate_f32": [i64, i64, i32, dp, dp],
-        "orc_emulate_f16": [i64, i64, i32, dp, dp],
+        "orc_table_dir": [i64, i32, i32, dp, dp, dp],
+        "orc_fft64": [i64, i64, i32, dp, dp],
+        "orc_dft64": [i64, i64, i32, dp, dp],
+        "orc_emulate_f64": [i64, i64, i32, i32, dp, dp],
+        "orc_emulate_f32": [i64, i64, i32, i32, dp, dp],
+        "orc_emulate_f16": [i64, i64, i32, i32, dp, dp],
         "orc_rn16_array": [i64, dp, dp],
         "orc_f16_to_double_array": [i64, dp, dp],
     }.items():
@@ -99,14 +100,15 @@ def theta(k: int, n: int) -> float:
     return float(_load().orc_theta(k, n))
 
 
-def table(n: int, kind="dual_select"):
-    """FP64 table for k in [0, n/2): (mult, ratio, path) with path 0 = cos, 1 = sin."""
+def table(n: int, kind="dual_select", inverse: bool = False):
+    """FP64 table for k in [0, n/2): (mult, ratio, path) with path 0 = cos, 1 = sin.
+    ``inverse``: the table of the inverse transform (conjugate twiddles)."""
     lib = _load()
     h = n // 2
     mult = np.empty(h, np.float64)
     ratio = np.empty(h, np.float64)
     path = np.empty(h, np.int32)
-    if lib.orc_table(n, _kind(kind), _ptr(mult), _ptr(ratio), _ptr(path)) != 0:
+    if lib.orc_table_dir(n, _kind(kind), int(inverse), _ptr(mult), _ptr(ratio), _ptr(path)) != 0:
         raise ValueError(f"bad table request n={n} kind={kind}")
     return mult, ratio, path
 
@@ -119,43 +121,46 @@ def _as_batch(x: np.ndarray, dtype) -> np.ndarray:
     return x
 
 
-def fft64(x: np.ndarray) -> np.ndarray:
-    """Radix-2 Stockham FFT in FP64 with the standard 10-flop butterfly."""
+def fft64(x: np.ndarray, inverse: bool = False) -> np.ndarray:
+    """Radix-2 Stockham FFT in FP64 with the standard 10-flop butterfly
+    (``inverse``: twiddles W^{-k}, unnormalised)."""
     x = _as_batch(x, np.float64)
     out = np.empty_like(x)
-    if _load().orc_fft64(x.shape[1], x.shape[0], _ptr(x), _ptr(out)) != 0:
+    if _load().orc_fft64(x.shape[1], x.shape[0], int(inverse), _ptr(x), _ptr(out)) != 0:
         raise ValueError("fft64 failed")
     return out
 
 
-def dft64(x: np.ndarray) -> np.ndarray:
-    """Brute-force O(N^2) DFT of eq. (1) in FP64."""
+def dft64(x: np.ndarray, inverse: bool = False) -> np.ndarray:
+    """Brute-force O(N^2) DFT of eq. (1) in FP64 (``inverse``: exponent sign +)."""
     x = _as_batch(x, np.float64)
     out = np.empty_like(x)
-    if _load().orc_dft64(x.shape[1], x.shape[0], _ptr(x), _ptr(out)) != 0:
+    if _load().orc_dft64(x.shape[1], x.shape[0], int(inverse), _ptr(x), _ptr(out)) != 0:
         raise ValueError("dft64 failed")
     return out
 
 
-def emulate(x: np.ndarray, kind="dual_select", prec: str = "f16") -> np.ndarray:
-    """Six-FMA butterfly FFT with every FMA rounded once to ``prec``.
+def emulate(x: np.ndarray, kind="dual_select", prec: str = "f16", inverse: bool = False) -> np.ndarray:
+    """Six-FMA butterfly FFT with every FMA rounded once to ``prec``
+    (``inverse``: the inverse transform, with the conjugate tables).
 
     ``x`` holds values of the working precision: float16 for "f16", float32 for
     "f32", float64 for "f64"; the result has the same dtype.
     """
     lib = _load()
+    inv = int(inverse)
     if prec == "f16":
         x = _as_batch(x, np.float16)
         out = np.empty_like(x)
-        rc = lib.orc_emulate_f16(x.shape[1], x.shape[0], _kind(kind), _ptr(x), _ptr(out))
+        rc = lib.orc_emulate_f16(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
     elif prec == "f32":
         x = _as_batch(x, np.float32)
         out = np.empty_like(x)
-        rc = lib.orc_emulate_f32(x.shape[1], x.shape[0], _kind(kind), _ptr(x), _ptr(out))
+        rc = lib.orc_emulate_f32(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
     elif prec == "f64":
         x = _as_batch(x, np.float64)
         out = np.empty_like(x)
-        rc = lib.orc_emulate_f64(x.shape[1], x.shape[0], _kind(kind), _ptr(x), _ptr(out))
+        rc = lib.orc_emulate_f64(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
     else:
         raise ValueError(prec)
     if rc != 0:
@@ -179,9 +184,9 @@ def fma32(a: float, b: float, c: float) -> float:
     return float(_load().orc_fma32(a, b, c))
 
 
-def rounded_table(n: int, kind="dual_select", prec: str = "f16"):
+def rounded_table(n: int, kind="dual_select", prec: str = "f16", inverse: bool = False):
     """The table rounded once from FP64 to the working precision."""
-    mult, ratio, path = table(n, kind)
+    mult, ratio, path = table(n, kind, inverse)
     if prec == "f16":
         return rn16(mult), rn16(ratio), path
     if prec == "f32":

@@ -22,6 +22,12 @@
  *     each FMA rounded once to the working precision (FP16, FP32, or FP64);
  *   - a direct double -> binary16 round-to-nearest-even conversion.
  *
+ * The inverse transform (x[n] = sum_k X[k] W^{-nk}, unnormalised) uses the
+ * conjugate twiddles W^{-k} = (w_r, -w_i); its tables follow the same rules
+ * (selection, clamp) applied to them.  The paper names only the round trip
+ * (Sec. V, binary32 relative L2 of about 1e-7); the inverse it implies is
+ * this one.
+ *
  * Readings taken where the paper is silent or misprinted:
  *   - theta = -(2*pi*k)/N evaluated in FP64 in that order (Algorithm 1 does not
  *     fix the order); cos/sin from the C library.
@@ -79,11 +85,12 @@ double orc_theta(int64_t k, int64_t n) {
  *       others are Linzer-Feig.
  * Returns 0, or -1 on a bad argument.
  */
-int orc_table(int64_t n, int kind, double* mult, double* ratio, int32_t* path) {
+int orc_table_dir(int64_t n, int kind, int inverse, double* mult, double* ratio, int32_t* path) {
     if (!is_pow2(n) || kind < 0 || kind > 3) return -1;
     for (int64_t k = 0; k < n / 2; ++k) {
         double th = orc_theta(k, n);
         double wr = cos(th), wi = sin(th);
+        if (inverse) wi = -wi;                  /* W^{-k}: the conjugate */
         int use_cos;
         if (kind == K_DUAL_SELECT) use_cos = fabs(wr) >= fabs(wi);
         else if (kind == K_COSINE) use_cos = 1;
@@ -102,6 +109,10 @@ int orc_table(int64_t n, int kind, double* mult, double* ratio, int32_t* path) {
         }
     }
     return 0;
+}
+
+int orc_table(int64_t n, int kind, double* mult, double* ratio, int32_t* path) {
+    return orc_table_dir(n, kind, 0, mult, ratio, path);
 }
 
 /* ---------------------------------------------------------------- binary16 */
@@ -237,13 +248,14 @@ static void stockham_emulate(int64_t n, int prec, const double* mult, const doub
 }
 
 /* Table rounded once from FP64 to the working precision. */
-static int rounded_table(int64_t n, int kind, int prec, double** mult, double** ratio, int32_t** path) {
+static int rounded_table(int64_t n, int kind, int inverse, int prec, double** mult, double** ratio,
+                         int32_t** path) {
     int64_t h = n / 2;
     *mult = (double*)malloc(sizeof(double) * h);
     *ratio = (double*)malloc(sizeof(double) * h);
     *path = (int32_t*)malloc(sizeof(int32_t) * h);
     if (!*mult || !*ratio || !*path) return -1;
-    if (orc_table(n, kind, *mult, *ratio, *path)) return -1;
+    if (orc_table_dir(n, kind, inverse, *mult, *ratio, *path)) return -1;
     for (int64_t k = 0; k < h; ++k) {
         (*mult)[k] = round_p(prec, (*mult)[k]);
         (*ratio)[k] = round_p(prec, (*ratio)[k]);
@@ -251,11 +263,11 @@ static int rounded_table(int64_t n, int kind, int prec, double** mult, double** 
     return 0;
 }
 
-static int emulate_batch(int64_t n, int64_t batch, int kind, int prec,
+static int emulate_batch(int64_t n, int64_t batch, int kind, int inverse, int prec,
                          const double* in, double* out) {
     if (!is_pow2(n) || batch < 0) return -1;
     double *mult, *ratio; int32_t* path;
-    if (rounded_table(n, kind, prec, &mult, &ratio, &path)) return -1;
+    if (rounded_table(n, kind, inverse, prec, &mult, &ratio, &path)) return -1;
     int err = 0;
 #pragma omp parallel
     {
@@ -278,32 +290,33 @@ static int emulate_batch(int64_t n, int64_t batch, int kind, int prec,
     return err;
 }
 
-/* FP64 emulation of the six-FMA butterflies (each FMA rounded to FP64). */
-int orc_emulate_f64(int64_t n, int64_t batch, int kind, const double* in, double* out) {
-    return emulate_batch(n, batch, kind, PREC_F64, in, out);
+/* FP64 emulation of the six-FMA butterflies (each FMA rounded to FP64);
+ * inverse != 0 runs the inverse transform (conjugate tables). */
+int orc_emulate_f64(int64_t n, int64_t batch, int kind, int inverse, const double* in, double* out) {
+    return emulate_batch(n, batch, kind, inverse, PREC_F64, in, out);
 }
 
 /* FP32 emulation: interleaved float in/out, each FMA rounded once to FP32. */
-int orc_emulate_f32(int64_t n, int64_t batch, int kind, const float* in, float* out) {
+int orc_emulate_f32(int64_t n, int64_t batch, int kind, int inverse, const float* in, float* out) {
     size_t cnt = (size_t)(2 * n * batch);
     double* a = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
     double* b = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
     if (!a || !b) { free(a); free(b); return -1; }
     for (size_t i = 0; i < cnt; ++i) a[i] = (double)in[i];
-    int rc = emulate_batch(n, batch, kind, PREC_F32, a, b);
+    int rc = emulate_batch(n, batch, kind, inverse, PREC_F32, a, b);
     for (size_t i = 0; i < cnt && rc == 0; ++i) out[i] = (float)b[i];
     free(a); free(b);
     return rc;
 }
 
 /* FP16 emulation: interleaved binary16 bit patterns in/out. */
-int orc_emulate_f16(int64_t n, int64_t batch, int kind, const uint16_t* in, uint16_t* out) {
+int orc_emulate_f16(int64_t n, int64_t batch, int kind, int inverse, const uint16_t* in, uint16_t* out) {
     size_t cnt = (size_t)(2 * n * batch);
     double* a = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
     double* b = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
     if (!a || !b) { free(a); free(b); return -1; }
     for (size_t i = 0; i < cnt; ++i) a[i] = orc_f16_to_double(in[i]);
-    int rc = emulate_batch(n, batch, kind, PREC_F16, a, b);
+    int rc = emulate_batch(n, batch, kind, inverse, PREC_F16, a, b);
     for (size_t i = 0; i < cnt && rc == 0; ++i) out[i] = orc_rn16(b[i]);
     free(a); free(b);
     return rc;
@@ -315,7 +328,7 @@ int orc_emulate_f16(int64_t n, int64_t batch, int kind, const uint16_t* in, uint
  * Plain radix-2 Stockham FFT in FP64 with the 10-flop butterfly of
  * eqs. (std1)-(std2): A = a + (w_r b_r - w_i b_i, w_i b_r + w_r b_i), B = a - (...).
  */
-int orc_fft64(int64_t n, int64_t batch, const double* in, double* out) {
+int orc_fft64(int64_t n, int64_t batch, int inverse, const double* in, double* out) {
     if (!is_pow2(n) || batch < 0) return -1;
     int64_t h2 = n / 2;
     double* wr = (double*)malloc(sizeof(double) * h2);
@@ -324,7 +337,7 @@ int orc_fft64(int64_t n, int64_t batch, const double* in, double* out) {
     for (int64_t k = 0; k < h2; ++k) {
         double th = orc_theta(k, n);
         wr[k] = cos(th);
-        wi[k] = sin(th);
+        wi[k] = inverse ? -sin(th) : sin(th);
     }
     int mlog = log2i(n);
     int err = 0;
@@ -366,8 +379,9 @@ int orc_fft64(int64_t n, int64_t batch, const double* in, double* out) {
     return err;
 }
 
-/* The DFT of eq. (1) written out: X[k] = sum_n x[n] exp(-j 2 pi (n k mod N) / N). */
-int orc_dft64(int64_t n, int64_t batch, const double* in, double* out) {
+/* The DFT of eq. (1) written out: X[k] = sum_n x[n] exp(-j 2 pi (n k mod N) / N);
+ * inverse != 0: exp(+j 2 pi (n k mod N) / N). */
+int orc_dft64(int64_t n, int64_t batch, int inverse, const double* in, double* out) {
     if (n < 1 || batch < 0) return -1;
 #pragma omp parallel for schedule(static)
     for (int64_t b = 0; b < batch; ++b) {
@@ -377,7 +391,7 @@ int orc_dft64(int64_t n, int64_t batch, const double* in, double* out) {
             double sr = 0.0, si = 0.0;
             for (int64_t t = 0; t < n; ++t) {
                 double th = orc_theta((t * k) % n, n);
-                double c = cos(th), s = sin(th);
+                double c = cos(th), s = inverse ? -sin(th) : sin(th);
                 sr += x[2 * t] * c - x[2 * t + 1] * s;
                 si += x[2 * t] * s + x[2 * t + 1] * c;
             }

@@ -48,6 +48,8 @@ _SIGS = {
     "fft_execute": ([_vp, _vp, _vp, _vp], _int),
     "fft_destroy": ([_vp], None),
     "fft_table_build": ([_i64, _int, _int, _vp, _vp, _vp], _int),
+    "fft_table_build_dir": ([_i64, _int, _int, _int, _vp, _vp, _vp], _int),
+    "fft_plan_create_dir": ([_i64, _i64, _int, _int, _int], _vp),
     "fft_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int),
                        ctypes.POINTER(_int), ctypes.c_char_p, _sz], _int),
     "fft_plan_workspace_bytes": ([_vp, ctypes.POINTER(_sz)], _int),
@@ -108,6 +110,21 @@ def fft_plan_create(n: int, batch: int, dtype, kind) -> int:
     return h
 
 
+FFT_FORWARD, FFT_INVERSE = -1, 1
+_DIRECTIONS = {"forward": FFT_FORWARD, "inverse": FFT_INVERSE}
+
+
+def _dir(direction) -> int:
+    return _DIRECTIONS[direction] if isinstance(direction, str) else int(direction)
+
+
+def fft_plan_create_dir(n: int, batch: int, dtype, kind, direction) -> int:
+    h = _lib.fft_plan_create_dir(n, batch, _dt(dtype), _kd(kind), _dir(direction))
+    if not h:
+        raise FFTError(FFT_EINVAL, fft_last_error())
+    return h
+
+
 def fft_plan_create_variant(n: int, batch: int, dtype, kind, variant_a: int = 0,
                             variant_b: int = 0, two_pass: bool = False) -> int:
     h = _lib.fft_plan_create_variant(n, batch, _dt(dtype), _kd(kind), variant_a, variant_b,
@@ -125,7 +142,7 @@ def fft_destroy(plan: int) -> None:
     _lib.fft_destroy(plan)
 
 
-def fft_table_build(n: int, dtype, kind):
+def fft_table_build(n: int, dtype, kind, direction="forward"):
     """(mult, ratio, path) of the size-n table rounded to dtype (host only)."""
     dt = _dt(dtype)
     h = n // 2
@@ -133,8 +150,8 @@ def fft_table_build(n: int, dtype, kind):
     mult = np.empty(h, st)
     ratio = np.empty(h, st)
     path = np.empty(h, np.uint8)
-    _check(_lib.fft_table_build(n, dt, _kd(kind), mult.ctypes.data, ratio.ctypes.data,
-                                path.ctypes.data))
+    _check(_lib.fft_table_build_dir(n, dt, _kd(kind), _dir(direction), mult.ctypes.data,
+                                    ratio.ctypes.data, path.ctypes.data))
     if dt == FFT_F16:
         mult, ratio = mult.view(np.float16), ratio.view(np.float16)
     return mult, ratio, path
@@ -297,12 +314,16 @@ def _check_tensor(t, n: int, batch: int, dt: int):
 class Plan:
     """Owns a plan handle; execute() takes torch tensors laid out (batch, n, 2)."""
 
-    def __init__(self, n: int, batch: int, dtype="f16", kind="dual_select", variant=None):
+    def __init__(self, n: int, batch: int, dtype="f16", kind="dual_select", variant=None,
+                 direction="forward"):
         self.n, self.batch, self.dtype, self.kind = n, batch, _dt(dtype), _kd(kind)
+        self.direction = _dir(direction)
         if variant is None:
-            self.handle = fft_plan_create(n, batch, self.dtype, self.kind)
-        else:
+            self.handle = fft_plan_create_dir(n, batch, self.dtype, self.kind, self.direction)
+        elif self.direction == FFT_FORWARD:
             self.handle = fft_plan_create_variant(n, batch, self.dtype, self.kind, *variant)
+        else:
+            raise FFTError(FFT_EINVAL, "explicit kernel variants are forward-only")
 
     def execute(self, x, y, stream=None) -> None:
         _check_tensor(x, self.n, self.batch, self.dtype)

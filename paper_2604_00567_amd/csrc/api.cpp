@@ -39,26 +39,26 @@ DeviceTable::~DeviceTable() {
 }
 
 static std::mutex g_table_mu;
-static std::map<std::tuple<int, int, int>, std::shared_ptr<DeviceTable>> g_tables;
+static std::map<std::tuple<int, int, int, int>, std::shared_ptr<DeviceTable>> g_tables;
 
 // Level-ordered table with capacity >= n for (device, dtype, kind), shared by
 // every plan that needs it.  A larger request replaces the cached table; plans
 // holding the old one keep it alive.
 static std::vector<std::shared_ptr<DeviceTable>> g_retired_tables;
 
-int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out) {
+int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     std::lock_guard<std::mutex> lock(g_table_mu);
-    auto key = std::make_tuple(dev, dtype, kind);
+    auto key = std::make_tuple(dev, dtype, kind, (int)inverse);
     auto it = g_tables.find(key);
     if (it != g_tables.end() && it->second->ncap >= n) {
         *out = it->second;
         return FFT_OK;
     }
     const int64_t ncap = std::max<int64_t>(n, 4096);
-    std::vector<uint8_t> img = build_level_table(ncap, dtype, kind);
+    std::vector<uint8_t> img = build_level_table(ncap, dtype, kind, inverse);
     auto t = std::make_shared<DeviceTable>();
     t->ncap = ncap;
     t->bytes = img.size();
@@ -191,7 +191,8 @@ int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
 
 static bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
 
-fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants) {
+fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants,
+                      bool inverse) {
     if (!is_pow2(n) || n > (int64_t(1) << 20)) {
         set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
         return nullptr;
@@ -213,6 +214,7 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
     p->batch = batch;
     p->dtype = dtype;
     p->kind = kind;
+    p->inverse = inverse;
     p->log_n = 0;
     while ((int64_t(1) << p->log_n) < n) ++p->log_n;
     hipError_t e = hipGetDevice(&p->device);
@@ -220,7 +222,7 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
         hip_error(e, "hipGetDevice");
         return nullptr;
     }
-    if (get_table(n, dtype, kind, &p->table) != FFT_OK) return nullptr;
+    if (get_table(n, dtype, kind, inverse, &p->table) != FFT_OK) return nullptr;
     int tuned[3];
     if (!variants && tuned_choice(dtype, p->log_n, tuned)) {
         // a recorded tuning choice; fall back to the fixed rule if it no longer exists
@@ -294,20 +296,37 @@ fft_plan* fft_plan_create(int64_t n, int64_t batch, fft_dtype dtype, fft_table_k
     return plan_create(n, batch, (int)dtype, (int)kind, nullptr);
 }
 
+fft_plan* fft_plan_create_dir(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                              int direction) {
+    if (direction != FFT_FORWARD && direction != FFT_INVERSE) {
+        set_error(FFT_EINVAL, "direction must be FFT_FORWARD or FFT_INVERSE");
+        return nullptr;
+    }
+    return plan_create(n, batch, (int)dtype, (int)kind, nullptr, direction == FFT_INVERSE);
+}
+
 int fft_execute(fft_plan* plan, const void* in, void* out, void* stream) {
     return plan_execute(plan, in, out, (hipStream_t)stream);
 }
 
 void fft_destroy(fft_plan* plan) { delete plan; }
 
-int fft_table_build(int64_t n, fft_dtype dtype, fft_table_kind kind, void* mult_out,
-                    void* ratio_out, uint8_t* path_out) {
+int fft_table_build_dir(int64_t n, fft_dtype dtype, fft_table_kind kind, int direction,
+                        void* mult_out, void* ratio_out, uint8_t* path_out) {
     if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
         return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
     if ((int)dtype != DT_F16 && (int)dtype != DT_F32) return set_error(FFT_EINVAL, "bad dtype");
     if ((int)kind < 0 || (int)kind > 3) return set_error(FFT_EINVAL, "bad table kind");
-    build_flat_table(n, (int)dtype, (int)kind, mult_out, ratio_out, path_out);
+    if (direction != FFT_FORWARD && direction != FFT_INVERSE)
+        return set_error(FFT_EINVAL, "direction must be FFT_FORWARD or FFT_INVERSE");
+    build_flat_table(n, (int)dtype, (int)kind, direction == FFT_INVERSE, mult_out, ratio_out,
+                     path_out);
     return FFT_OK;
+}
+
+int fft_table_build(int64_t n, fft_dtype dtype, fft_table_kind kind, void* mult_out,
+                    void* ratio_out, uint8_t* path_out) {
+    return fft_table_build_dir(n, dtype, kind, FFT_FORWARD, mult_out, ratio_out, path_out);
 }
 
 int fft_plan_info(const fft_plan* p, int64_t* n, int64_t* batch, int* dtype, int* kind,

@@ -354,7 +354,7 @@ fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, co
         hip_error(e, "hipGetDevice");
         return nullptr;
     }
-    if (get_table(nmax, dtype, kind, &b->table) != FFT_OK) return nullptr;
+    if (get_table(nmax, dtype, kind, false, &b->table) != FFT_OK) return nullptr;
     if (build_items(b.get()) != FFT_OK) return nullptr;
     if (upload(b.get()) != FFT_OK) return nullptr;
     if ((e = hipEventCreateWithFlags(&b->last, hipEventDisableTiming)) != hipSuccess) {

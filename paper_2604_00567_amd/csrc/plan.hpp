@@ -19,7 +19,8 @@ struct DeviceTable {
 
 int set_error(int code, const std::string& msg);
 int hip_error(hipError_t e, const char* where);
-int get_table(int64_t n, int dtype, int kind, std::shared_ptr<DeviceTable>* out);
+// The shared device table of (device, dtype, kind, direction) covering size n.
+int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out);
 const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant);
 int count_kernels(int dtype, int mode, int log_nu);
 std::string describe(const KernelCfg* k);
@@ -30,6 +31,7 @@ int elem_bytes(int dtype);
 struct fft_plan {
     int64_t n = 0, batch = 0;
     int log_n = 0, dtype = 0, kind = 0, device = 0;
+    bool inverse = false;                   // inverse transform (conjugate tables)
     std::shared_ptr<dsfft::DeviceTable> table;
     const dsfft::KernelCfg* k1 = nullptr;   // single kernel, or the column kernel
     const dsfft::KernelCfg* k1_plain = nullptr;  // k1's size without 16-byte staging
@@ -43,7 +45,8 @@ struct fft_plan {
 };
 
 namespace dsfft {
-fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants);
+fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants,
+                      bool inverse = false);
 bool tuned_choice(int dtype, int log_n, int* variants);
 int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
 }  // namespace dsfft

@@ -72,7 +72,7 @@ fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int6
     for (int m = 1; m <= 13; ++m) s->cfg_choice[m] = kSmallCfg[m];
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) { hip_error(e, "hipGetDevice"); return nullptr; }
-    if (get_table(int64_t(1) << 18, s->dtype, s->kind, &s->table) != FFT_OK) return nullptr;
+    if (get_table(int64_t(1) << 18, s->dtype, s->kind, false, &s->table) != FFT_OK) return nullptr;
     if ((e = hipMalloc(&s->d_items, sizeof(HostBatchItem) * max_items)) != hipSuccess ||
         (e = hipMalloc(&s->d_offs, sizeof(int64_t) * max_transforms)) != hipSuccess ||
         (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * 2)) != hipSuccess ||

@@ -10,15 +10,17 @@ namespace dsfft {
 
 static constexpr double kEpsClamp = 1e-7;   // Linzer-Feig clamp of sin(theta)
 
-// Entry k of the size-n table in FP64.  theta = -(2 pi k)/n, w_r = cos, w_i = sin.
+// Entry k of the size-n table in FP64.  theta = -(2 pi k)/n, w_r = cos, w_i = sin;
+// for the inverse transform the twiddle is the conjugate W^{-k} = (w_r, -w_i)
+// and the same rules below apply to it.
 //   dual-select (Algorithm 1): |w_r| >= |w_i| -> (w_r, w_i/w_r, cosine path),
 //                              else (w_i, w_r/w_i, sine path);   |ratio| <= 1.
 //   Linzer-Feig (Sec. II-B):   (w_i', w_r/w_i', sine) with w_i' = +1e-7 if |w_i| < 1e-7.
 //   cosine (Sec. II-C):        (w_r, w_i/w_r, cosine).
 //   Linzer-Feig, W^0 exempt:   k = 0 on the cosine path, the rest Linzer-Feig.
-Twiddle64 twiddle64(int64_t k, int64_t n, int kind) {
+Twiddle64 twiddle64(int64_t k, int64_t n, int kind, bool inverse) {
     const double angle = -((2.0 * M_PI) * (double)k) / (double)n;
-    const double wr = std::cos(angle), wi = std::sin(angle);
+    const double wr = std::cos(angle), wi = inverse ? -std::sin(angle) : std::sin(angle);
     bool cos_path;
     switch (kind) {
         case TABLE_DUAL_SELECT: cos_path = std::fabs(wr) >= std::fabs(wi); break;
@@ -103,18 +105,19 @@ static void pack_entry(const Twiddle64& t, int dtype, uint8_t* dst) {
 
 size_t entry_bytes(int dtype) { return dtype == DT_F16 ? 8 : 16; }
 
-std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind) {
+std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind, bool inverse) {
     const size_t eb = entry_bytes(dtype);
     std::vector<uint8_t> img((size_t)ncap * eb, 0);
     for (int64_t L = 2; L <= ncap; L <<= 1)
         for (int64_t j = 0; j < L / 2; ++j)
-            pack_entry(twiddle64(j, L, kind), dtype, img.data() + (size_t)(L / 2 + j) * eb);
+            pack_entry(twiddle64(j, L, kind, inverse), dtype, img.data() + (size_t)(L / 2 + j) * eb);
     return img;
 }
 
-void build_flat_table(int64_t n, int dtype, int kind, void* mult, void* ratio, uint8_t* path) {
+void build_flat_table(int64_t n, int dtype, int kind, bool inverse, void* mult, void* ratio,
+                      uint8_t* path) {
     for (int64_t k = 0; k < n / 2; ++k) {
-        const Twiddle64 t = twiddle64(k, n, kind);
+        const Twiddle64 t = twiddle64(k, n, kind, inverse);
         if (dtype == DT_F16) {
             const uint16_t m = f64_to_f16(t.mult), r = f64_to_f16(t.ratio);
             if (mult) std::memcpy((uint8_t*)mult + 2 * k, &m, 2);

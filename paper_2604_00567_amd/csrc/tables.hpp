@@ -17,15 +17,17 @@ struct Twiddle64 {
     bool sine;     // false: cosine factorisation, true: sine factorisation
 };
 
-Twiddle64 twiddle64(int64_t k, int64_t n, int kind);
+Twiddle64 twiddle64(int64_t k, int64_t n, int kind, bool inverse);
 uint16_t f64_to_f16(double x);
 size_t entry_bytes(int dtype);
 
-// Device image with entry L/2 + j = T_L[j] for L = 2 .. ncap (entry 0 unused).
-std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind);
+// Device image with entry L/2 + j = T_L[j] for L = 2 .. ncap (entry 0 unused);
+// `inverse`: the tables of the inverse transform (conjugate twiddles).
+std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind, bool inverse);
 
 // Flat table T_n[k], k < n/2: rounded mult and ratio (binary16 bits or float)
 // and the path byte (0 cosine, 1 sine).  Null outputs are skipped.
-void build_flat_table(int64_t n, int dtype, int kind, void* mult, void* ratio, uint8_t* path);
+void build_flat_table(int64_t n, int dtype, int kind, bool inverse, void* mult, void* ratio,
+                      uint8_t* path);
 
 }  // namespace dsfft

@@ -31,6 +31,28 @@ def test_host_tables_match_oracle(dtype, kind):
         assert np.array_equal(p_lib, p_orc.astype(np.uint8)), n
 
 
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("kind", ["dual_select", "linzer_feig", "cosine", "lf_w0_exempt"])
+def test_host_inverse_tables_match_oracle(dtype, kind):
+    view = np.uint16 if dtype == "f16" else np.uint32
+    for m in (1, 2, 3, 5, 10, 12, 20):
+        n = 1 << m
+        m_lib, r_lib, p_lib = binding.fft_table_build(n, dtype, kind, "inverse")
+        m_orc, r_orc, p_orc = oracle.rounded_table(n, kind, dtype, inverse=True)
+        assert np.array_equal(m_lib.view(view), m_orc.view(view)), n
+        assert np.array_equal(r_lib.view(view), r_orc.view(view)), n
+        assert np.array_equal(p_lib, p_orc.astype(np.uint8)), n
+
+
+def test_direction_validation_without_gpu():
+    with pytest.raises(binding.FFTError):
+        binding.fft_table_build(64, "f16", "dual_select", 0)
+    assert "direction" in binding.fft_last_error()
+    with pytest.raises(binding.FFTError):
+        binding.fft_plan_create_dir(64, 1, "f16", "dual_select", 2)
+    assert "direction" in binding.fft_last_error()
+
+
 def test_dual_select_table_facts_in_storage_precision():
     # Table I: at N = 1024 the stored dual-select ratio peaks at exactly 1.0,
     # the paths split 256 / 256, and the clamped Linzer-Feig entry overflows binary16
