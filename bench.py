@@ -15,7 +15,8 @@ with batch * N = 2^26 (binary16 and binary32); the binary32 single-size case
 N = 1024 x 16 with all table kinds; the uneven batch of 4096 transforms with
 N = 2^U, U uniform over 6..16, in one graph replay (two persistent kernels),
 against one plan per size class; the serving
-loop on Poisson arrivals at 20k requests/s against one launch per request;
+loop on Poisson arrivals at 20k requests/s (and at 80k requests/s) against
+one launch per request;
 and the CPU oracle on the host cores.  Prints one JSON line.
 """
 from __future__ import annotations
@@ -297,10 +298,10 @@ def bench_single_fp32(torch, binding, inputs):
     return out
 
 
-def bench_serving(torch, seconds: float, seed: int = 9):
+def bench_serving(torch, seconds: float, seed: int = 9, rate: float = 20000.0):
     from paper_2604_00567_amd import inputs
     from paper_2604_00567_amd.serve import Server, run_per_request
-    tr = inputs.poisson_trace(20000.0, seconds, seed)
+    tr = inputs.poisson_trace(rate, seconds, seed)
     srv = Server(slots=4, budget_bytes=64 << 30, slot_bytes=1 << 30, seed=seed)
     try:
         cont = srv.run(tr)
@@ -308,8 +309,11 @@ def bench_serving(torch, seconds: float, seed: int = 9):
         srv.close()
     torch.cuda.empty_cache()
     base = run_per_request(tr, streams=4, seed=seed)
-    return {"trace": f"Poisson 20000 req/s for {seconds:g} s ({tr['t'].size} requests), "
+    offered = float(np.sum([2 * n * b * (4 if d == "f16" else 8)
+                            for n, b, d in zip(tr["n"], tr["batch"], tr["dtype"])]) / seconds / 1e9)
+    return {"trace": f"Poisson {rate:g} req/s for {seconds:g} s ({tr['t'].size} requests), "
                      "N=2^8..2^18, batch 1..64, 75% f16 / 25% f32, N(0,1) generated on the GPU",
+            "offered_gbs": round(offered, 1),
             "continuous": cont, "one_launch_per_request": base}
 
 
@@ -439,8 +443,9 @@ def main():
         result["single_fp32"] = bench_single_fp32(torch, binding, inputs)
         torch.cuda.empty_cache()
         if args.serve_seconds > 0:
-            log(f"serving, {args.serve_seconds:g} s of trace")
+            log(f"serving, {args.serve_seconds:g} s of trace at 20k req/s, 2 s at 80k req/s")
             result["serving"] = bench_serving(torch, args.serve_seconds)
+            result["serving_high_load"] = bench_serving(torch, 2.0, seed=10, rate=80000.0)
     bufs.clear()
     if not args.no_cpu:
         log("cpu baseline (oracle emulation)")

@@ -177,15 +177,15 @@ int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* ro
  * 2 .. 2^18), packed back to back in the order given (transform i starts at
  * element sum_{j<i} n[j]).  Every transform is computed exactly as
  * fft_plan_create would (same butterflies, same table), but all of them run
- * in two persistent work-queue kernels: sizes up to 2^13 as whole-transform
- * work items, 2^14 .. 2^18 as the column items and row items of the
+ * in two persistent work-queue kernels: sizes up to 2^14 as whole-transform
+ * work items, 2^15 .. 2^18 as the column items and row items of the
  * two-pass schedule.  The first kernel runs every column item and every
  * whole-transform item, the second every row item; the launch boundary
- * orders each transform's row items after its column items.  The three
- * launches (queue-head reset, first kernel, second kernel) form one HIP graph
- * built at the first execute and replayed by every execute; new data
- * pointers are set on the graph's kernel nodes.  The batch owns a workspace
- * of sum of the sizes >= 2^14 elements.  Returns NULL on error.
+ * orders each transform's row items after its column items.  The two
+ * launches form one HIP graph built at the first execute and replayed by
+ * every execute (the kernels leave their work-queue counters at zero for the
+ * next replay); new data pointers are set on the graph's kernel nodes.  The batch owns a workspace
+ * of sum of the sizes >= 2^15 elements.  Returns NULL on error.
  */
 fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, fft_table_kind kind);
 
@@ -235,7 +235,7 @@ int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int
  * uneven-batch kernels over the requests admitted in one scheduling step of a
  * continuous-batching server (the same butterflies and tables as every other
  * entry point).  Capacities: max_items work items, max_transforms
- * single-unit transforms, max_large transforms of 2^14 points or more, and
+ * single-unit transforms, max_large transforms of 2^15 points or more, and
  * ws_bytes of workspace for them.  Returns NULL on error.
  */
 fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int64_t max_items,

@@ -16,18 +16,20 @@
 namespace dsfft {
 
 // Single-unit configuration per log2 N (1..13) and units per workgroup.
-const int kSmallCfg[14] = {-1, HB_N2, HB_N4, HB_N8, HB_N16, HB_N32, HB_N64, HB_N128,
-                                  HB_N256, HB_N512, HB_N1024, HB_N2048, HB_N4096, HB_N8192};
+const int kSmallCfg[kMaxSingleLog + 1] = {-1, HB_N2, HB_N4, HB_N8, HB_N16, HB_N32, HB_N64, HB_N128,
+                                          HB_N256, HB_N512, HB_N1024, HB_N2048, HB_N4096, HB_N8192,
+                                          HB_N16384};
 int cfg_upw(int cfg) {
     switch (cfg) {
         case HB_N2: case HB_N4: case HB_N8: return 512;
         case HB_N16: case HB_N32: return 128;
-        case HB_N64: case HB_N128: case HB_COLS128: case HB_ROWS128: case HB_COLS256:
+        case HB_N64: case HB_N128: case HB_ROWS128: case HB_COLS256:
         case HB_ROWS256: return 64;
         case HB_N256: case HB_N512: case HB_COLS512: case HB_ROWS512: return 32;
         case HB_N1024: return 16;
         case HB_N2048: case HB_N1024_B: return 8;
         case HB_N4096_B: return 4;
+        case HB_N16384: return 1;
         default: return 2;       // HB_N4096, HB_N8192
     }
 }
@@ -73,14 +75,14 @@ fft_batch::~fft_batch() {
 
 namespace dsfft {
 
-// Column/row split of a large transform: configurations and log2 of the
-// column count (column kernel) and row count (row kernel).
+// Column/row split of a transform of 2^15 .. 2^18 points (smaller ones are
+// whole-transform items): configurations and log2 of the column count
+// (column kernel) and row count (row kernel).
 struct Split {
     int ccfg, rcfg, lm_c, lm_r;
 };
 static Split split_for(int m) {
     switch (m) {
-        case 14: return {HB_COLS128, HB_ROWS128, 7, 7};
         case 15: return {HB_COLS256, HB_ROWS128, 7, 8};
         case 16: return {HB_COLS256, HB_ROWS256, 8, 8};
         case 17: return {HB_COLS512, HB_ROWS256, 8, 9};
@@ -105,7 +107,7 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
     for (int64_t t = 0; t < count; ++t) {
         int m = 0;
         while ((int64_t(1) << m) < n[t]) ++m;
-        if (m <= 13) {
+        if (m <= kMaxSingleLog) {
             by_class[m].push_back(off[t]);
             continue;
         }
@@ -139,7 +141,7 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
         ws_elems += n[t];
         ++slot;
     }
-    for (int m = 13; m >= 1; --m) {
+    for (int m = kMaxSingleLog; m >= 1; --m) {
         const auto& v = by_class[m];
         if (v.empty()) continue;
         const int cfg = cfg_choice[m];
@@ -191,7 +193,7 @@ static int upload(fft_batch* b) {
     const size_t ob = std::max<size_t>(1, b->offs.size()) * sizeof(int64_t);
     if ((e = hipMalloc(&b->d_items, ib)) != hipSuccess) return hip_error(e, "hipMalloc(items)");
     if ((e = hipMalloc(&b->d_offs, ob)) != hipSuccess) return hip_error(e, "hipMalloc(offsets)");
-    if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * 2)) != hipSuccess)
+    if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * kQueueWords)) != hipSuccess)
         return hip_error(e, "hipMalloc(control)");
     if (b->ws_bytes && (e = hipMalloc(&b->ws, b->ws_bytes)) != hipSuccess)
         return e == hipErrorOutOfMemory ? set_error(FFT_ENOMEM, "batch workspace allocation failed")
@@ -204,8 +206,9 @@ static int upload(fft_batch* b) {
         (e = hipMemcpy(b->d_offs, b->offs.data(), b->offs.size() * sizeof(int64_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_error(e, "hipMemcpy(offsets)");
-    if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * 2)) != hipSuccess)
-        return hip_error(e, "hipMemset(queue heads)");
+    if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * kQueueWords)) != hipSuccess)
+        return hip_error(e, "hipMemset(queue words)");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
     const int64_t n1 = (int64_t)b->items.size() - b->phase0;
     b->grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(b->phase0, b->resident));
     b->grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, b->resident));
@@ -229,7 +232,7 @@ struct PhaseArgs {
         : in(in_), out(out_), ws(b->ws), lt(b->table->ptr), items(b->d_items), offs(b->d_offs),
           first(phase == 0 ? 0 : (int)b->phase0),
           nitems(phase == 0 ? (int)b->phase0 : (int)((int64_t)b->items.size() - b->phase0)),
-          head(b->d_ctl + phase) {
+          head(b->d_ctl + 2 * phase) {
         void* p[9] = {&in, &out, &ws, &lt, &items, &offs, &first, &nitems, &head};
         std::copy(p, p + 9, slots);
     }
@@ -246,30 +249,17 @@ static hipKernelNodeParams phase_params(const fft_batch* b, PhaseArgs& a, int ph
     return kp;
 }
 
-// Builds the graph once: queue-head reset, phase 0, phase 1 (each a
-// persistent kernel), in that order.
+// Builds the graph once: phase 0, then phase 1 (each a persistent kernel).
 static int build_graph(fft_batch* b, const void* in, void* out) {
     hipError_t e;
     if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_error(e, "hipGraphCreate");
-    unsigned* ctl = b->d_ctl;
-    int nheads = 2;
-    void* rargs[] = {&ctl, &nheads};
-    hipKernelNodeParams rp{};
-    rp.func = const_cast<void*>(batch_reset_func());
-    rp.gridDim = dim3(1);
-    rp.blockDim = dim3(64);
-    rp.sharedMemBytes = 0;
-    rp.kernelParams = rargs;
-    rp.extra = nullptr;
-    hipGraphNode_t reset = nullptr;
-    if ((e = hipGraphAddKernelNode(&reset, b->graph, nullptr, 0, &rp)) != hipSuccess)
-        return hip_error(e, "hipGraphAddKernelNode(reset)");
-    hipGraphNode_t prev = reset;
+    hipGraphNode_t prev = nullptr;
     for (int ph = 0; ph < 2; ++ph) {
         PhaseArgs a(b, in, out, ph);
         if (a.nitems == 0) continue;
         hipKernelNodeParams kp = phase_params(b, a, ph);
-        if ((e = hipGraphAddKernelNode(&b->knode[ph], b->graph, &prev, 1, &kp)) != hipSuccess)
+        if ((e = hipGraphAddKernelNode(&b->knode[ph], b->graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                       &kp)) != hipSuccess)
             return hip_error(e, "hipGraphAddKernelNode(phase)");
         prev = b->knode[ph];
     }
@@ -344,7 +334,7 @@ fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, co
         b->total += v;
         nmax = std::max(nmax, v);
     }
-    for (int m = 1; m <= 13; ++m) b->cfg_choice[m] = kSmallCfg[m];
+    for (int m = 1; m <= kMaxSingleLog; ++m) b->cfg_choice[m] = kSmallCfg[m];
     if (choice) {
         if (choice[0] == HB_N1024 || choice[0] == HB_N1024_B) b->cfg_choice[10] = choice[0];
         if (choice[1] == HB_N4096 || choice[1] == HB_N4096_B) b->cfg_choice[12] = choice[1];

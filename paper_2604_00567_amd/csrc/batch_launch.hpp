@@ -22,13 +22,14 @@ enum HostBatchCfg {
     HB_N2 = 0, HB_N4, HB_N8, HB_N16, HB_N32, HB_N64, HB_N128, HB_N256, HB_N512, HB_N1024,
     HB_N2048, HB_N4096, HB_N8192,
     HB_N1024_B, HB_N4096_B,
-    HB_COLS128, HB_ROWS128, HB_COLS256, HB_ROWS256, HB_COLS512, HB_ROWS512,
+    HB_ROWS128, HB_COLS256, HB_ROWS256, HB_COLS512, HB_ROWS512, HB_N16384,
     HB_COUNT
 };
 
 constexpr int kHostBatchThreads = 512;
 
-extern const int kSmallCfg[14];        // single-unit configuration per log2 N (1..13)
+constexpr int kMaxSingleLog = 14;      // sizes up to 2^14 run as whole-transform items
+extern const int kSmallCfg[kMaxSingleLog + 1];   // their configuration per log2 N (1..14)
 int cfg_upw(int cfg);                  // units per workgroup of a configuration
 
 // Work list for transforms of sizes n[t] at element offsets off[t] (batch.cpp):
@@ -41,14 +42,15 @@ int batch_resident_grid(int dtype, int device, int* out);
 
 size_t batch_lds_bytes(int dtype);
 const void* batch_kernel_func(int dtype);
-const void* batch_reset_func();
-hipError_t launch_batch_reset(unsigned* ctl, int n, hipStream_t s);
-// One phase: items first .. first + nitems - 1, queue head *head.
+// Queue words per batch or serving slot: (head, workgroups done) for each of
+// the two phases; zero when allocated, and left zero by every launch.
+constexpr int kQueueWords = 4;
+// One phase: items first .. first + nitems - 1, queue words q[0..1].
 hipError_t launch_batch(int dtype, const void* in, void* out, void* ws, const void* lt,
                         const void* items, const int64_t* offs, int first, int nitems,
-                        unsigned* head, int grid, hipStream_t s);
-// Both phases of a work list (reset of the two queue heads ctl[0..1], then
-// phase 0 and phase 1) on stream s.
+                        unsigned* q, int grid, hipStream_t s);
+// Both phases of a work list (phase 0 on ctl[0..1], phase 1 on ctl[2..3]) on
+// stream s.
 hipError_t launch_batch_phases(int dtype, const void* in, void* out, void* ws, const void* lt,
                                const void* items, const int64_t* offs, int phase0, int nitems,
                                unsigned* ctl, int grid0, int grid1, hipStream_t s);

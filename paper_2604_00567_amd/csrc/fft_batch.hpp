@@ -3,8 +3,8 @@
 // is one workgroup's worth of units of one size class and runs the same
 // register-pass / LDS-exchange code as the regular kernels.
 //
-// Transforms up to 2^13 points are single-unit items (whole transforms).
-// Larger ones (2^14 .. 2^18) use the two-kernel split of the global schedule:
+// Transforms up to 2^14 points are single-unit items (whole transforms).
+// Larger ones (2^15 .. 2^18) use the two-kernel split of the global schedule:
 // column items (stages 1..log2 N1, into a workspace) and row items (the
 // remaining stages, into the output).  The work list has two phases, each
 // run by one launch of the persistent kernel: phase 0 = every column item,
@@ -98,7 +98,8 @@ constexpr int batch_lds_elems() {
         8 * PassPlan<11, 5, 3, 3>::region(), 2 * PassPlan<12, 4, 4, 4>::region(),
         2 * PassPlan<13, 5, 4, 4>::region(), 8 * PassPlan<10, 4, 3, 3>::region(),
         4 * PassPlan<12, 5, 4, 3>::region(), 64 * PassPlan<7, 4, 3, 0>::region(),
-        64 * PassPlan<8, 5, 3, 0>::region(), 32 * PassPlan<9, 5, 4, 0>::region()};
+        64 * PassPlan<8, 5, 3, 0>::region(), 32 * PassPlan<9, 5, 4, 0>::region(),
+        1 * PassPlan<14, 5, 5, 4>::region()};
     for (int s : sizes) m = s > m ? s : m;
     return m;
 }
@@ -123,23 +124,26 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
         case HB_N8192: batch_unit<E, 13, 5, 2, MODE_SMALL, 5, 4, 4>(lds, lt, in, out, g); break;
         case HB_N1024_B: batch_unit<E, 10, 4, 8, MODE_SMALL, 4, 3, 3>(lds, lt, in, out, g); break;
         case HB_N4096_B: batch_unit<E, 12, 5, 4, MODE_SMALL, 5, 4, 3>(lds, lt, in, out, g); break;
-        case HB_COLS128: batch_unit<E, 7, 4, 64, MODE_COLS, 4, 3, 0>(lds, lt, in, ws, g); break;
         case HB_ROWS128: batch_unit<E, 7, 4, 64, MODE_ROWS, 4, 3, 0>(lds, lt, ws, out, g); break;
         case HB_COLS256: batch_unit<E, 8, 5, 64, MODE_COLS, 5, 3, 0>(lds, lt, in, ws, g); break;
         case HB_ROWS256: batch_unit<E, 8, 5, 64, MODE_ROWS, 5, 3, 0>(lds, lt, ws, out, g); break;
         case HB_COLS512: batch_unit<E, 9, 5, 32, MODE_COLS, 5, 4, 0>(lds, lt, in, ws, g); break;
         case HB_ROWS512: batch_unit<E, 9, 5, 32, MODE_ROWS, 5, 4, 0>(lds, lt, ws, out, g); break;
+        case HB_N16384: batch_unit<E, 14, 5, 1, MODE_SMALL, 5, 5, 4>(lds, lt, in, out, g); break;
         default: break;
     }
 }
 
-// Items first .. first + nitems - 1 of one phase; *head is the phase's queue
-// head (zero at launch).
+// Items first .. first + nitems - 1 of one phase.  q[0] is the phase's queue
+// head and q[1] counts the workgroups that have left the loop; both are zero
+// at launch, and the last workgroup to leave sets them back to zero for the
+// next launch on the stream (so no clearing launch is needed).
 template <class E>
 __global__ void __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(sizeof(E) == 4 ? 4 : 2)))
 fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __restrict__ lt,
                  const BatchItem* __restrict__ items, const int64_t* __restrict__ offs,
-                 int first, int nitems, unsigned* head) {
+                 int first, int nitems, unsigned* q) {
+    unsigned* head = q;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     // Claims run one item ahead: the claim of the next item is issued when
@@ -169,12 +173,12 @@ fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __res
         __syncthreads();   // LDS consumed before the next item reuses it; next claim visible
         idx = __builtin_amdgcn_readfirstlane(s_item[k & 1]);
     }
-}
-
-// Clears the queue heads (a kernel rather than a memset node, so the graph
-// holds kernels only).
-__global__ void batch_reset_kernel(unsigned* ctl, int n) {
-    for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < n; i += blockDim.x * gridDim.x) ctl[i] = 0u;
+    // This workgroup's claims are over (its last one returned an index past
+    // the end).  The last workgroup out sees every claim made and resets.
+    if (threadIdx.x == 0 && atomicAdd(&q[1], 1u) == gridDim.x - 1) {
+        atomicExch(&q[0], 0u);
+        atomicExch(&q[1], 0u);
+    }
 }
 
 }  // namespace dsfft

@@ -17,25 +17,18 @@ const void* batch_kernel_func(int dtype) {
     return dtype == 0 ? (const void*)&fft_batch_kernel<uint32_t> : (const void*)&fft_batch_kernel<f2_t>;
 }
 
-const void* batch_reset_func() { return (const void*)&batch_reset_kernel; }
-
-hipError_t launch_batch_reset(unsigned* ctl, int n, hipStream_t s) {
-    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(64), 0, s, ctl, n);
-    return hipGetLastError();
-}
-
 hipError_t launch_batch(int dtype, const void* in, void* out, void* ws, const void* lt,
                         const void* items, const int64_t* offs, int first, int nitems,
-                        unsigned* head, int grid, hipStream_t s) {
+                        unsigned* q, int grid, hipStream_t s) {
     if (dtype == 0) {
         hipLaunchKernelGGL(fft_batch_kernel<uint32_t>, dim3(grid), dim3(kBatchThreads),
                            batch_lds_bytes_t<uint32_t>(), s, (const uint32_t*)in, (uint32_t*)out,
                            (uint32_t*)ws, (const TwH*)lt, (const BatchItem*)items, offs, first, nitems,
-                           head);
+                           q);
     } else {
         hipLaunchKernelGGL(fft_batch_kernel<f2_t>, dim3(grid), dim3(kBatchThreads),
                            batch_lds_bytes_t<f2_t>(), s, (const f2_t*)in, (f2_t*)out, (f2_t*)ws,
-                           (const TwF*)lt, (const BatchItem*)items, offs, first, nitems, head);
+                           (const TwF*)lt, (const BatchItem*)items, offs, first, nitems, q);
     }
     return hipGetLastError();
 }
@@ -43,11 +36,11 @@ hipError_t launch_batch(int dtype, const void* in, void* out, void* ws, const vo
 hipError_t launch_batch_phases(int dtype, const void* in, void* out, void* ws, const void* lt,
                                const void* items, const int64_t* offs, int phase0, int nitems,
                                unsigned* ctl, int grid0, int grid1, hipStream_t s) {
-    hipError_t e = launch_batch_reset(ctl, 2, s);
-    if (e == hipSuccess && phase0 > 0)
+    hipError_t e = hipSuccess;
+    if (phase0 > 0)
         e = launch_batch(dtype, in, out, ws, lt, items, offs, 0, phase0, ctl, grid0, s);
     if (e == hipSuccess && nitems > phase0)
-        e = launch_batch(dtype, in, out, ws, lt, items, offs, phase0, nitems - phase0, ctl + 1,
+        e = launch_batch(dtype, in, out, ws, lt, items, offs, phase0, nitems - phase0, ctl + 2,
                          grid1, s);
     return e;
 }

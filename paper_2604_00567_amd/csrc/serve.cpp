@@ -1,11 +1,13 @@
-// Serving slots: one in-flight launch of the persistent batch kernel over the
+// Serving slots: one in-flight launch of the persistent batch kernels over the
 // requests admitted in one scheduling step.  The work list is built on the
-// host, staged through pinned memory and copied to the slot's device buffers
-// on the slot's stream, so consecutive steps on different slots overlap on
-// the device.
+// host, packed with the transform offsets into one pinned staging buffer and
+// copied to the slot's device buffer with one copy on the slot's stream, so
+// a step costs one copy and one launch per phase, and consecutive steps on
+// different slots overlap on the device.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -17,12 +19,10 @@
 struct fft_serve_slot {
     int dtype = 0, kind = 0, device = 0;
     std::shared_ptr<dsfft::DeviceTable> table;
-    dsfft::HostBatchItem* d_items = nullptr;
-    int64_t* d_offs = nullptr;
+    uint8_t* d_stage = nullptr;              // items, then the offsets
     unsigned* d_ctl = nullptr;
     void* ws = nullptr;
-    dsfft::HostBatchItem* h_items = nullptr;   // pinned staging
-    int64_t* h_offs = nullptr;
+    uint8_t* h_stage = nullptr;              // pinned staging of the same layout
     int64_t item_cap = 0, offs_cap = 0;
     int slot_cap = 0;
     size_t ws_cap = 0;
@@ -40,12 +40,10 @@ fft_serve_slot::~fft_serve_slot() {
         if (launched) (void)hipEventSynchronize(done);
         (void)hipEventDestroy(done);
     }
-    if (d_items) (void)hipFree(d_items);
-    if (d_offs) (void)hipFree(d_offs);
+    if (d_stage) (void)hipFree(d_stage);
     if (d_ctl) (void)hipFree(d_ctl);
     if (ws) (void)hipFree(ws);
-    if (h_items) (void)hipHostFree(h_items);
-    if (h_offs) (void)hipHostFree(h_offs);
+    if (h_stage) (void)hipHostFree(h_stage);
 }
 
 using namespace dsfft;
@@ -69,17 +67,21 @@ fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int6
     s->offs_cap = max_transforms;
     s->slot_cap = max_large;
     s->ws_cap = ws_bytes;
-    for (int m = 1; m <= 13; ++m) s->cfg_choice[m] = kSmallCfg[m];
+    for (int m = 1; m <= kMaxSingleLog; ++m) s->cfg_choice[m] = kSmallCfg[m];
     hipError_t e = hipGetDevice(&s->device);
     if (e != hipSuccess) { hip_error(e, "hipGetDevice"); return nullptr; }
     if (get_table(int64_t(1) << 18, s->dtype, s->kind, false, &s->table) != FFT_OK) return nullptr;
-    if ((e = hipMalloc(&s->d_items, sizeof(HostBatchItem) * max_items)) != hipSuccess ||
-        (e = hipMalloc(&s->d_offs, sizeof(int64_t) * max_transforms)) != hipSuccess ||
-        (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * 2)) != hipSuccess ||
+    const size_t stage = sizeof(HostBatchItem) * max_items + sizeof(int64_t) * max_transforms;
+    if ((e = hipMalloc(&s->d_stage, stage)) != hipSuccess ||
+        (e = hipMalloc(&s->d_ctl, sizeof(unsigned) * kQueueWords)) != hipSuccess ||
         (ws_bytes && (e = hipMalloc(&s->ws, ws_bytes)) != hipSuccess) ||
-        (e = hipHostMalloc((void**)&s->h_items, sizeof(HostBatchItem) * max_items, 0)) != hipSuccess ||
-        (e = hipHostMalloc((void**)&s->h_offs, sizeof(int64_t) * max_transforms, 0)) != hipSuccess) {
+        (e = hipHostMalloc((void**)&s->h_stage, stage, 0)) != hipSuccess) {
         set_error(e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP, "serving slot allocation failed");
+        return nullptr;
+    }
+    if ((e = hipMemset(s->d_ctl, 0, sizeof(unsigned) * kQueueWords)) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        hip_error(e, "hipMemset(queue words)");
         return nullptr;
     }
     if (batch_resident_grid(s->dtype, s->device, &s->resident) != FFT_OK) return nullptr;
@@ -114,7 +116,7 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
             s->tn.push_back(v);
             s->toff.push_back(off[r] + j * v);
         }
-        if (v >= (int64_t(1) << 14)) nlarge += batch[r];
+        if (v >= (int64_t(1) << 15)) nlarge += batch[r];
     }
     int64_t ws_elems = 0, phase0 = 0;
     build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice, s->items,
@@ -123,19 +125,17 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
         nlarge > s->slot_cap || (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
         return set_error(FFT_ENOMEM, "step exceeds the slot's capacity");
     if (s->items.empty()) return FFT_OK;
-    std::copy(s->items.begin(), s->items.end(), s->h_items);
-    std::copy(s->offs.begin(), s->offs.end(), s->h_offs);
-    if ((e = hipMemcpyAsync(s->d_items, s->h_items, sizeof(HostBatchItem) * s->items.size(),
+    const size_t ib = sizeof(HostBatchItem) * s->items.size();   // a multiple of 8
+    std::memcpy(s->h_stage, s->items.data(), ib);
+    std::memcpy(s->h_stage + ib, s->offs.data(), sizeof(int64_t) * s->offs.size());
+    if ((e = hipMemcpyAsync(s->d_stage, s->h_stage, ib + sizeof(int64_t) * s->offs.size(),
                             hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_error(e, "hipMemcpyAsync(items)");
-    if (!s->offs.empty() &&
-        (e = hipMemcpyAsync(s->d_offs, s->h_offs, sizeof(int64_t) * s->offs.size(),
-                            hipMemcpyHostToDevice, st)) != hipSuccess)
-        return hip_error(e, "hipMemcpyAsync(offsets)");
+        return hip_error(e, "hipMemcpyAsync(work list)");
     const int64_t n1 = (int64_t)s->items.size() - phase0;
     const int grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(phase0, s->resident));
     const int grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, s->resident));
-    if ((e = launch_batch_phases(s->dtype, data, data, s->ws, s->table->ptr, s->d_items, s->d_offs,
+    if ((e = launch_batch_phases(s->dtype, data, data, s->ws, s->table->ptr, s->d_stage,
+                                 (const int64_t*)(s->d_stage + ib),
                                  (int)phase0, (int)s->items.size(), s->d_ctl, grid0, grid1, st)) !=
         hipSuccess)
         return hip_error(e, "launch(batch)");

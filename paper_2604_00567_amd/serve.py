@@ -28,7 +28,7 @@ from . import binding
 
 ELEM_BYTES = {"f16": 4, "f32": 8}
 TORCH_DTYPE = {"f16": torch.float16, "f32": torch.float32}
-LARGE = 1 << 14          # transforms this size and up use the column/row split
+LARGE = 1 << 15          # transforms this size and up use the column/row split
 
 
 def latency_summary(latency_s: np.ndarray) -> dict:
@@ -247,9 +247,11 @@ class Server:
         return out
 
 
-def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", seed: int = 0) -> dict:
+def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", seed: int = 0,
+                    budget_bytes: int = 64 << 30) -> dict:
     """Same trace, one launch per request (cached regular plans), round-robin
-    over `streams` streams."""
+    over `streams` streams, admitted in arrival order under the same HBM
+    budget as the continuous loop (request bytes in flight)."""
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     sts = [torch.cuda.Stream() for _ in range(streams)]
@@ -260,13 +262,16 @@ def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", se
           zip(trace["n"], trace["batch"], trace["dtype"])]
     done_t = np.full(total, np.nan)
     inflight = {}
+    inflight_bytes = 0
+    max_inflight = 0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     nxt, completed, k = 0, 0, 0
     while completed < total:
         now = time.perf_counter() - t0
         progressed = False
-        while nxt < total and t_arr[nxt] <= now:
+        while nxt < total and t_arr[nxt] <= now and (
+                inflight_bytes + nb[nxt] <= budget_bytes or not inflight):
             n, b, dt = int(trace["n"][nxt]), int(trace["batch"][nxt]), str(trace["dtype"][nxt])
             key = (n, b, dt)
             if key not in plans:
@@ -280,12 +285,15 @@ def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", se
                 ev = torch.cuda.Event()
                 ev.record(st)
             inflight[nxt] = (ev, buf)
+            inflight_bytes += nb[nxt]
+            max_inflight = max(max_inflight, inflight_bytes)
             nxt += 1
             progressed = True
         for rid in list(inflight.keys()):
             if inflight[rid][0].query():
                 done_t[rid] = time.perf_counter() - t0
                 del inflight[rid]
+                inflight_bytes -= nb[rid]
                 completed += 1
                 progressed = True
         if not progressed:
@@ -295,5 +303,6 @@ def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", se
     wall = np.nanmax(done_t) - t_arr[0]
     out = latency_summary(done_t - t_arr)
     out.update({"requests": int(total), "launches": int(total),
-                "gbs": float(np.sum(nb) / wall / 1e9), "wall_s": float(wall), "streams": streams})
+                "gbs": float(np.sum(nb) / wall / 1e9), "wall_s": float(wall), "streams": streams,
+                "max_inflight_bytes": int(max_inflight), "budget_bytes": int(budget_bytes)})
     return out

@@ -10,7 +10,7 @@ from paper_2604_00567_amd import binding, inputs
 
 F = {k: i for i, k in enumerate(binding.WORK_FIELDS)}
 # units per item and log2 NU of each configuration id (order of HostBatchCfg)
-CFG_LOGNU = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 10, 12, 7, 7, 8, 8, 9, 9]
+CFG_LOGNU = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 10, 12, 7, 8, 8, 9, 9, 14]
 
 
 def classify(it):
@@ -26,7 +26,7 @@ def check(sizes):
     items, phase0, offs, ws = binding.fft_batch_work_list(sizes)
     assert np.all(items[:phase0, F["phase"]] == 0) and np.all(items[phase0:, F["phase"]] == 1)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    large = sizes >= (1 << 14)
+    large = sizes >= (1 << 15)
     assert ws == int(sizes[large].sum())
 
     # single-unit transforms: each start exactly once, with the class's config

@@ -350,7 +350,7 @@ def test_batch_small_configs_index_math(name):
     assert np.max(np.abs(out - ref)) < 1e-9 * n
 
 
-@pytest.mark.parametrize("cols,rows", [("HB_COLS128", "HB_ROWS128"), ("HB_COLS256", "HB_ROWS128"),
+@pytest.mark.parametrize("cols,rows", [("HB_COLS256", "HB_ROWS128"),
                                        ("HB_COLS256", "HB_ROWS256"), ("HB_COLS512", "HB_ROWS256"),
                                        ("HB_COLS512", "HB_ROWS512")])
 def test_batch_two_pass_index_math(cols, rows):
