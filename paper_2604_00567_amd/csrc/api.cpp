@@ -122,7 +122,9 @@ std::string describe(const KernelCfg* k) {
                   "%s:nu=2^%d,e=2^%d,upw=%d,r=[%d,%d,%d],stg=%d,lane=%d,pipe=%d,t=%d,lds=%zu",
                   modes[k->mode], k->log_nu, k->log_e, k->upw, k->lr[0], k->lr[1], k->lr[2],
                   k->staged, k->lane_tail, k->pipelined, k->threads, k->lds_bytes);
-    return buf;
+    std::string d = buf;
+    if (k->upl > 1) d += ",upl=" + std::to_string(k->upl);
+    return d;
 }
 
 // Largest single-kernel size per dtype (a binary16 transform of 2^15 points,

@@ -83,7 +83,7 @@ __device__ __forceinline__ void batch_unit(E* lds, const typename TwOf<E>::type*
     BatchGeo g = geo;
     g.lane_id = (int)threadIdx.x;
     asm volatile("" : "+v"(g.lane_id));
-    unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, g);
+    unit_pass<E, LOG_NU, LOG_E, UPW, 1, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, g);
 }
 
 // Largest LDS footprint over the batch configurations, in elements.

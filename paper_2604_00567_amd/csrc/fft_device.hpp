@@ -322,10 +322,17 @@ struct GridGeo {
     }
 };
 
+// Lanes and units.  A lane holds groups of UPL units (units per lane): the
+// same group positions g + G u of units ul0 .. ul0 + UPL - 1, so each twiddle
+// it loads serves all of them.  Its registers hold unit k's elements at
+// v[k * EL .. k * EL + EL).  Column units and the row kernel's last pass map
+// consecutive lanes to consecutive units ("unit-fast", UPL = 1 only); every
+// other pass maps consecutive lanes to consecutive groups of one unit.
+
 // Pass-0 inputs of this lane straight from HBM (unstaged configurations):
 // group r = g + G u (residue r, span 1) takes elements r + M i, i < R.
 // The streaming hint is used only where a wave's accesses cover whole lines.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int LANE,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int LANE,
           class Geo>
 __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
@@ -337,29 +344,33 @@ __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
     constexpr int GPL = EL / R;
     constexpr bool unit_fast = (MODE == MODE_COLS);
     const int tid = gp.tid();
-    const int ul = unit_fast ? (tid % UPW) : (tid / G);
+    const int ul0 = unit_fast ? (tid % UPW) : (tid / G) * UPL;
     const int g = unit_fast ? (tid / UPW) : (tid % G);
-    if (gp.active(ul)) {
-        const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul);
 #pragma unroll
-        for (int u = 0; u < GPL; ++u) {
-            const int r = g + G * u;
+    for (int k = 0; k < UPL; ++k) {
+        E* vk = v + k * EL;
+        if (gp.active(ul0 + k)) {
+            const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul0 + k);
 #pragma unroll
-            for (int i = 0; i < R; ++i) {
-                const int64_t idx = r + (int64_t)M * i;
-                const E* src = in + geo.base_in + idx * geo.in_stride;
-                v[u * R + i] = (MODE != MODE_COLS) ? __builtin_nontemporal_load(src) : *src;
+            for (int u = 0; u < GPL; ++u) {
+                const int r = g + G * u;
+#pragma unroll
+                for (int i = 0; i < R; ++i) {
+                    const int64_t idx = r + (int64_t)M * i;
+                    const E* src = in + geo.base_in + idx * geo.in_stride;
+                    vk[u * R + i] = (MODE != MODE_COLS) ? __builtin_nontemporal_load(src) : *src;
+                }
             }
-        }
-    } else {
+        } else {
 #pragma unroll
-        for (int k = 0; k < EL; ++k) v[k] = E{};
+            for (int e = 0; e < EL; ++e) vk[e] = E{};
+        }
     }
 }
 
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
 // LR radix-2 stages per group, scatter (LDS or global).
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PRE, int P, class Geo>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
                                           const E* in, E* out, const Geo& gp) {
@@ -377,17 +388,18 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr int LOGM = PP::log_m(P);
         constexpr int M = 1 << LOGM;
         constexpr int GPL = EL / R;
-        constexpr int NT_OF = UPW * G;
+        constexpr int NT_OF = (UPW / UPL) * G;
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
+        static_assert(UPL == 1 || (MODE == MODE_SMALL && !LANE && UPW % UPL == 0),
+                      "several units per lane: whole-transform units without the lane tail");
         const int tid = gp.tid();
-        const int ul = unit_fast ? (tid % UPW) : (tid / G);
+        const int ul0 = unit_fast ? (tid % UPW) : (tid / G) * UPL;
         const int g0 = unit_fast ? (tid / UPW) : (tid % G);
         // lane-tail units: the last pass takes group (r, q) on lane q + 16 r
         constexpr bool lane_map = LANE && P == NP - 1;
         const int g = lane_map ? (((g0 & 15) << 2) | (g0 >> 4)) : g0;
-        const bool active = gp.active(ul);
-        E* reg = lds + ul * RS;
-        const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul);
+        // twiddle offsets of the row kernel (the same for every unit of a lane)
+        const UnitGeom geo0 = gp.template get<LOG_NU, MODE>(ul0);
 
         // ---- gather
         if constexpr (P == 0 && STG) {
@@ -397,30 +409,37 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
             // pass's decimated groups from LDS.
             stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, gp.block_first(LOG_NU),
                                               gp.block_units(UPW) << LOG_NU);
-            const E* nat = lds + ul * NU;
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int r = g + G * u;
+            for (int k = 0; k < UPL; ++k) {
+                const E* nat = lds + (ul0 + k) * NU;
 #pragma unroll
-                for (int i = 0; i < R; ++i) v[u * R + i] = nat[r + M * i];
+                for (int u = 0; u < GPL; ++u) {
+                    const int r = g + G * u;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) v[k * EL + u * R + i] = nat[r + M * i];
+                }
             }
         } else if constexpr (P == 0) {
-            if constexpr (!PRE) load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(v, in, gp);
+            if constexpr (!PRE) load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(v, in, gp);
         } else {
             constexpr int PADP = PP::pad(P - 1);
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int gam = g + G * u;
-                const int r = gam & (M - 1);
-                const int q = gam >> LOGM;
-                // local index r + M i + (NU/L0) q lives in row q of the exchange
-                const int basep = r + ((NU / L0) + PADP) * q;
+            for (int k = 0; k < UPL; ++k) {
+                const E* reg = lds + (ul0 + k) * RS;
 #pragma unroll
-                for (int i = 0; i < R; ++i) v[u * R + i] = reg[basep + M * i];
+                for (int u = 0; u < GPL; ++u) {
+                    const int gam = g + G * u;
+                    const int r = gam & (M - 1);
+                    const int q = gam >> LOGM;
+                    // local index r + M i + (NU/L0) q lives in row q of the exchange
+                    const int basep = r + ((NU / L0) + PADP) * q;
+#pragma unroll
+                    for (int i = 0; i < R; ++i) v[k * EL + u * R + i] = reg[basep + M * i];
+                }
             }
         }
 
-        // ---- twiddles and stages
+        // ---- twiddles (once per group position) and stages (for each unit)
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
             const int gam = g + G * u;
@@ -430,12 +449,13 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = lt[c];
             } else {
-                const int qg = geo.q0 + (q << geo.log_lb);
-                const int lg0 = L0 << geo.log_lb;
+                const int qg = geo0.q0 + (q << geo0.log_lb);
+                const int lg0 = L0 << geo0.log_lb;
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = lt[qg + lg0 * c];
             }
-            reg_pass<LR>(v + u * R, tw);
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw);
         }
 
         // ---- scatter
@@ -448,7 +468,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
             const int q = g0 & 15, r = (g0 >> 4) & 1, u = g0 >> 5;
             if constexpr (STG) {
                 __syncthreads();
-                E* nat = lds + ul * NU;
+                E* nat = lds + ul0 * NU;
 #pragma unroll
                 for (int k = 0; k < EL / 2; ++k) {
                     const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
@@ -458,58 +478,70 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 __syncthreads();
                 stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
                                                    gp.block_units(UPW) << LOG_NU);
-            } else if (active) {
+            } else if (gp.active(ul0)) {
 #pragma unroll
                 for (int k = 0; k < EL / 2; ++k) {
                     const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
-                    __builtin_nontemporal_store(v[2 * k], out + geo.base_out + jb);
-                    __builtin_nontemporal_store(v[2 * k + 1], out + geo.base_out + jb + NU / 2);
+                    __builtin_nontemporal_store(v[2 * k], out + geo0.base_out + jb);
+                    __builtin_nontemporal_store(v[2 * k + 1], out + geo0.base_out + jb + NU / 2);
                 }
             }
         } else if constexpr (P + 1 < NP) {
             constexpr int PAD = PP::pad(P);
             if constexpr (P > 0 || STG) __syncthreads();   // readers of LDS are done
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int gam = g + G * u;
-                const int r = gam & (M - 1);
-                const int q = gam >> LOGM;
-                // local index r + M (q + L0 e) lives in row q + L0 e
+            for (int k = 0; k < UPL; ++k) {
+                E* reg = lds + (ul0 + k) * RS;
 #pragma unroll
-                for (int e = 0; e < R; ++e) reg[r + (M + PAD) * (q + L0 * e)] = v[u * R + e];
+                for (int u = 0; u < GPL; ++u) {
+                    const int gam = g + G * u;
+                    const int r = gam & (M - 1);
+                    const int q = gam >> LOGM;
+                    // local index r + M (q + L0 e) lives in row q + L0 e
+#pragma unroll
+                    for (int e = 0; e < R; ++e)
+                        reg[r + (M + PAD) * (q + L0 * e)] = v[k * EL + u * R + e];
+                }
             }
             __syncthreads();
         } else if constexpr (STG && MODE == MODE_SMALL) {
             // outputs to LDS in natural order, then 16-byte streaming stores
             // (row units stage only their input: their outputs are strided)
             __syncthreads();                      // every lane is done reading LDS
-            E* nat = lds + ul * NU;
 #pragma unroll
-            for (int u = 0; u < GPL; ++u) {
-                const int q = g + G * u;
+            for (int k = 0; k < UPL; ++k) {
+                E* nat = lds + (ul0 + k) * NU;
 #pragma unroll
-                for (int e = 0; e < R; ++e) nat[q + L0 * e] = v[u * R + e];
+                for (int u = 0; u < GPL; ++u) {
+                    const int q = g + G * u;
+#pragma unroll
+                    for (int e = 0; e < R; ++e) nat[q + L0 * e] = v[k * EL + u * R + e];
+                }
             }
             __syncthreads();
             stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
                                                gp.block_units(UPW) << LOG_NU);
         } else {
-            if (active) {
 #pragma unroll
-                for (int u = 0; u < GPL; ++u) {
-                    const int q = g + G * u;      // M = 1: every group is a column
+            for (int k = 0; k < UPL; ++k) {
+                if (gp.active(ul0 + k)) {
+                    const UnitGeom geo = gp.template get<LOG_NU, MODE>(ul0 + k);
 #pragma unroll
-                    for (int e = 0; e < R; ++e) {
-                        const int64_t idx = q + (int64_t)L0 * e;
-                        E* dst = out + geo.base_out + idx * geo.out_stride;
-                        if (MODE == MODE_SMALL) __builtin_nontemporal_store(v[u * R + e], dst);
-                        else *dst = v[u * R + e];
+                    for (int u = 0; u < GPL; ++u) {
+                        const int q = g + G * u;  // M = 1: every group is a column
+#pragma unroll
+                        for (int e = 0; e < R; ++e) {
+                            const int64_t idx = q + (int64_t)L0 * e;
+                            E* dst = out + geo.base_out + idx * geo.out_stride;
+                            if (MODE == MODE_SMALL) __builtin_nontemporal_store(v[k * EL + u * R + e], dst);
+                            else *dst = v[k * EL + u * R + e];
+                        }
                     }
                 }
             }
         }
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PRE, P + 1>(v, lds, lt, in,
-                                                                                     out, gp);
+        unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PRE, P + 1>(v, lds, lt, in,
+                                                                                           out, gp);
     }
 }
 
@@ -517,33 +549,33 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // lt: level-ordered table.  units: units in this launch.  log_m: log2(N/NU),
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
 __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
                                                  int64_t units, int log_m);
 
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
-__global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E))
+__global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E))
 fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
                                                                                   units, log_m);
 }
 
 // The pipelined kernel holds two register sets; the compiler is asked to fit
 // three waves per SIMD so the prefetch is not bought with occupancy.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
-__global__ void __launch_bounds__(UPW << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
+__global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
 fft_unit_kernel_pipe(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                      int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
                                                                                   units, log_m);
 }
 
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
 __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
@@ -555,13 +587,13 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE == 0 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
-    E v[1 << LOG_E];
+    E v[UPL << LOG_E];
     if constexpr (PIPE) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
         // in two register sets used alternately (a and b), so the next block's
         // HBM reads are in flight while the current block is computed and no
         // register copy forces an early wait
-        E vb[1 << LOG_E];
+        E vb[UPL << LOG_E];
         const int64_t nblk = (units + UPW - 1) / UPW;
         const int64_t step = gridDim.x;
         int64_t blk = blockIdx.x;
@@ -574,28 +606,28 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
             return GridGeo{b * UPW, units, log_m, t};
         };
         if (blk < nblk)
-            load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+            load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(
                 v, in, geo(blk));
         while (blk < nblk) {
             if (blk + step < nblk)
-                load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+                load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(
                     vb, in, geo(blk + step));
-            unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
+            unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
                 v, lds, lt, in, out, geo(blk));
             __syncthreads();    // LDS is reused by the next block
             blk += step;
             if (blk >= nblk) break;
             if (blk + step < nblk)
-                load_pass0<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>(
+                load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(
                     v, in, geo(blk + step));
-            unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
+            unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 1, 0>(
                 vb, lds, lt, in, out, geo(blk));
             __syncthreads();
             blk += step;
         }
     } else {
         const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
-        unit_pass<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
+        unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }
 }

@@ -15,8 +15,9 @@ struct KernelCfg {
     int dtype;      // DT_F16 / DT_F32
     int mode;       // MODE_SMALL / MODE_COLS / MODE_ROWS
     int log_nu;     // unit size (log2)
-    int log_e;      // elements per lane (log2)
+    int log_e;      // elements per lane and unit (log2)
     int upw;        // units per workgroup
+    int upl;        // units per lane (a lane's groups of one position in UPL units)
     int lr[3];      // register-pass radices (log2; 0 = absent)
     int staged;     // 1: block copied through LDS with 16-byte accesses
     int lane_tail;  // 1: the last two stages run across lanes (permlane swaps)

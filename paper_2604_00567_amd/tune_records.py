@@ -18,7 +18,8 @@ import sys
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", required=True)
-    ap.add_argument("--bytes", type=float, default=512e6, help="data bytes per timed execute")
+    ap.add_argument("--bytes", type=float, default=float(1 << 28),
+                    help="input bytes per timed execute (256 MiB: the batched workloads' size)")
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--log-min", type=int, default=1)
     ap.add_argument("--log-max", type=int, default=20)
@@ -34,7 +35,8 @@ def main():
             rep = binding.fft_tune(n, batch, dtype, "dual_select", reps=args.reps)
             best = max(rep, key=lambda c: c["GBs"])
             print(json.dumps({"n": n, "dtype": dtype, "batch": batch, "best": best,
-                              "candidates": len(rep)}), flush=True)
+                              "candidates": [(c["variant"], c["GBs"], c["config"]) for c in rep]}),
+                  flush=True)
     return 0
 
 

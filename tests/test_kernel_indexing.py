@@ -18,16 +18,19 @@ CONFIGS = os.path.join(os.path.dirname(os.path.dirname(__file__)),
 MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
 
 
-def load_configs():
+def load_configs(with_upl=False):
     out = []
     for line in open(CONFIGS):
-        m = re.match(r"\s*CFG\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
-                     r"\s*(\d+),\s*(\d+),\s*(\d+)\)", line)
+        m = re.match(r"\s*CFG(U?)\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
+                     r"\s*(\d+),\s*(\d+),\s*(\d+)(?:,\s*(\d+))?\)", line)
         if m:
-            mode = MODES[m.group(1)]
+            mode = MODES[m.group(2)]
+            upl = int(m.group(12)) if m.group(1) else 1
+            assert (upl != 1) == bool(m.group(1)) or upl == 1
             # the pipelined flag changes which workgroup takes a block, not a
             # block's index math (blocks b, b + grid, ... cover every block once)
-            out.append((mode,) + tuple(int(m.group(i)) for i in range(2, 10)))
+            cfg = (mode,) + tuple(int(m.group(i)) for i in range(3, 11))
+            out.append(cfg + (upl,) if with_upl else cfg)
     return out
 
 
@@ -286,7 +289,38 @@ def test_small_configs_index_math(cfg):
 def test_configs_parsed():
     cfgs = load_configs()
     text = open(CONFIGS).read()
-    assert len(cfgs) == text.count("\nCFG(") and len(cfgs) > 40
+    assert len(cfgs) == text.count("\nCFG(") + text.count("\nCFGU(") and len(cfgs) > 40
+
+
+def lane_units(tid, G, upw, upl):
+    """Units and group position of lane tid in a whole-transform workgroup
+    with upl units per lane (the kernel's mapping)."""
+    return [(tid // G) * upl + k for k in range(upl)], tid % G
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_configs(with_upl=True) if c[-1] > 1])
+def test_units_per_lane_mapping(cfg):
+    # (lane, k) -> (unit, group position) covers the workgroup's units and
+    # positions exactly once, as the one-unit-per-lane mapping of the same
+    # configuration does; every other index is that configuration's
+    mode, log_nu, log_e, upw = cfg[:4]
+    upl = cfg[-1]
+    assert mode == 0 and upw % upl == 0 and cfg[8] == 0
+    G = 1 << (log_nu - log_e)
+    nt = (upw // upl) * G
+    seen = set()
+    for tid in range(nt):
+        units, g = lane_units(tid, G, upw, upl)
+        for ul in units:
+            assert 0 <= ul < upw and 0 <= g < G
+            seen.add((ul, g))
+    assert seen == {(ul, g) for ul in range(upw) for g in range(G)}
+    # per unit, the lanes' work is the one-unit-per-lane configuration's
+    n = 1 << log_nu
+    x, out, written, _ = simulate(cfg[:9], n, upw + 1)
+    assert np.all(written == 1)
+    ref = np.fft.fft(x.reshape(upw + 1, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n
 
 
 def test_persistent_blocks_cover_once():
