@@ -153,6 +153,33 @@ def test_full_size_sampled(n, batch, samples):
     assert np.all(np.isfinite(y))
 
 
+@pytest.mark.parametrize("n,dtype,two_pass", [(1024, "f16", False), (1 << 16, "f16", True),
+                                              (4096, "f32", False)])
+def test_more_than_2e31_elements(n, dtype, two_pass):
+    """One launch over 2^31 + complex elements (8-16 GiB each way): every
+    element offset needs 64 bits.  A small distinct block is tiled over the
+    whole batch on the device; sampled transforms (the last ones included) are
+    compared with the oracle."""
+    torch = pytest.importorskip("torch")
+    total = (1 << 31) + (1 << 20)
+    batch = total // n
+    distinct = 32
+    x0 = inputs.uniform(n, distinct, 17, dtype)
+    xt = torch.from_numpy(x0).to("cuda:0").repeat((batch + distinct - 1) // distinct, 1, 1)[:batch]
+    yt = torch.empty_like(xt)
+    plan = binding.Plan(n, batch, dtype, "dual_select", variant=(0, 0, True) if two_pass else None)
+    try:
+        plan.execute(xt, yt)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    ref = oracle.emulate(x0, "dual_select", dtype)
+    for b in (0, 1, batch // 2, batch - 2, batch - 1):
+        assert mismatches(yt[b].cpu().numpy()[None], ref[b % distinct][None]) == 0, b
+    del xt, yt
+    torch.cuda.empty_cache()
+
+
 def test_argument_errors():
     torch = pytest.importorskip("torch")
     n, batch = 1024, 4
