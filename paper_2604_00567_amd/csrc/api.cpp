@@ -152,8 +152,9 @@ int choose_schedule(fft_plan* p, const int* variants) {
 int elem_bytes(int dtype) { return dtype == DT_F16 ? 4 : 8; }
 
 // Workspace: two-pass schedules stage the intermediate per chunk of
-// transforms; a chunk is capped at 64 MiB so the intermediate can stay in the
-// memory-side cache between the two kernels.
+// transforms, capped at 128 MiB (measured: 128 MiB chunks run 5-6 % faster
+// than 64 MiB or 1 GiB ones; 8 MiB chunks take twice as long, the kernels
+// being too short for their launch and tail).
 void size_workspace(fft_plan* p) {
     if (!p->k2) {
         p->chunk = p->batch;
@@ -161,7 +162,7 @@ void size_workspace(fft_plan* p) {
         return;
     }
     const size_t per = (size_t)p->n * elem_bytes(p->dtype);
-    const size_t cap = (size_t)64 << 20;
+    const size_t cap = (size_t)128 << 20;
     int64_t chunk = (int64_t)std::max<size_t>(1, cap / per);
     chunk = std::min<int64_t>(chunk, p->batch);
     p->chunk = chunk;

@@ -398,3 +398,22 @@ def test_batch_two_pass_index_math(cols, rows):
     assert np.all(w2 == 1)
     ref = np.fft.fft(x.reshape(batch, n), axis=1).ravel()
     assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_configs() if c[0] in (1, 2)])
+def test_every_column_and_row_config_index_math(cfg):
+    """Each column (row) configuration paired with a row (column) configuration
+    of the same size: the pair computes the DFT, every workspace and output
+    element written once."""
+    cfgs = load_configs()
+    mode = cfg[0]
+    # the smallest configuration of the other kind keeps the simulated size down
+    other = min((c for c in cfgs if c[0] == 3 - mode and c[7] == 0), key=lambda c: (c[1], c[3]))
+    cols, rows = (cfg, other) if mode == 1 else (other, cfg)
+    n = 1 << (cols[1] + rows[1])
+    x, ws, w1, _ = simulate(cols, n, 1)
+    assert np.all(w1 == 1)
+    _, out, w2, _ = simulate(rows, n, 1, x=ws)
+    assert np.all(w2 == 1)
+    ref = np.fft.fft(x.reshape(1, n), axis=1).ravel()
+    assert np.max(np.abs(out - ref)) < 1e-9 * n
