@@ -178,14 +178,17 @@ int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* ro
  * element sum_{j<i} n[j]).  Every transform is computed exactly as
  * fft_plan_create would (same butterflies, same table), but all of them run
  * in two persistent work-queue kernels: sizes up to 2^14 as whole-transform
- * work items, 2^15 .. 2^18 as the column items and row items of the
- * two-pass schedule.  The first kernel runs every column item and every
+ * work items, larger ones as the column items and row items of the two-pass
+ * schedule.  The first kernel runs every column item and every
  * whole-transform item, the second every row item; the launch boundary
- * orders each transform's row items after its column items.  The two
+ * orders each transform's row items after its column items.  Binary16
+ * transforms of 2^15 points (128 KiB, one workgroup's LDS) run whole in a
+ * kernel of their own, over a list of their offsets, before the two.  The
  * launches form one HIP graph built at the first execute and replayed by
  * every execute (the kernels leave their work-queue counters at zero for the
- * next replay); new data pointers are set on the graph's kernel nodes.  The batch owns a workspace
- * of sum of the sizes >= 2^15 elements.  Returns NULL on error.
+ * next replay); new data pointers are set on the graph's kernel nodes.  The
+ * batch owns a workspace of the summed sizes of its two-pass transforms.
+ * Returns NULL on error.
  */
 fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, fft_table_kind kind);
 
@@ -214,28 +217,31 @@ int fft_batch_info(const fft_batch* batch, int64_t* items, int64_t* grid, size_t
 /* Waits for the batch's last execution, then frees it.  NULL-safe. */
 void fft_batch_destroy(fft_batch* batch);
 
-/* The work list an uneven batch of sizes n[0..count) would run (host only,
- * no device call), for inspection and tests.  Transforms are packed in order
- * (offsets are prefix sums).  items_out receives 8 int64 per item: config
- * id, units, first unit (whole-transform items: first index into offs_out;
- * column and row items: first column or row), log2 of the column/row
- * count, phase (0: first kernel, 1: second kernel), large-transform index
- * (-1 for whole-transform items), input offset, output offset (column items
- * write, and row items read, the workspace).  The first *phase0 items are
- * phase 0.  offs_out receives the transform offsets of the whole-transform
- * items.  nitems, phase0, noffs and ws_elems (workspace elements) are always
- * set; with both output pointers NULL the call only reports the sizes;
+/* The work list an uneven batch of sizes n[0..count) and `dtype` would run
+ * (host only, no device call), for inspection and tests.  Transforms are
+ * packed in order (offsets are prefix sums).  items_out receives 8 int64 per
+ * item: config id, units, first unit (whole-transform items: first index into
+ * offs_out; column and row items: first column or row), log2 of the
+ * column/row count, phase (0: first kernel, 1: second kernel), large-transform
+ * index (-1 for whole-transform items), input offset, output offset (column
+ * items write, and row items read, the workspace).  The first *phase0 items
+ * are phase 0.  offs_out receives the transform offsets of the
+ * whole-transform items, list_out those of the transforms run by the list
+ * kernel.  nitems, phase0, noffs, nlist and ws_elems (workspace elements) are
+ * always set; with all output pointers NULL the call only reports the sizes;
  * FFT_EINVAL when a capacity is too small. */
-int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int64_t item_cap,
-                        int64_t* nitems, int64_t* phase0, int64_t* offs_out, int64_t offs_cap,
-                        int64_t* noffs, int64_t* ws_elems);
+int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_t* items_out,
+                        int64_t item_cap, int64_t* nitems, int64_t* phase0, int64_t* offs_out,
+                        int64_t offs_cap, int64_t* noffs, int64_t* list_out, int64_t list_cap,
+                        int64_t* nlist, int64_t* ws_elems);
 
 /*
  * Serving slot: the device and pinned buffers for one in-flight launch of the
  * uneven-batch kernels over the requests admitted in one scheduling step of a
  * continuous-batching server (the same butterflies and tables as every other
  * entry point).  Capacities: max_items work items, max_transforms
- * single-unit transforms, max_large transforms of 2^15 points or more, and
+ * whole transforms (work items and list kernel together), max_large
+ * transforms of 2^15 points or more, and
  * ws_bytes of workspace for them.  Returns NULL on error.
  */
 fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int64_t max_items,

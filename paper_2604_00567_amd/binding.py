@@ -62,8 +62,9 @@ _SIGS = {
     "fft_batch_elements": ([_vp, ctypes.POINTER(_i64)], _int),
     "fft_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
     "fft_batch_destroy": ([_vp], None),
-    "fft_batch_work_list": ([_vp, _i64, _vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64), _vp,
-                             _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)], _int),
+    "fft_batch_work_list": ([_vp, _i64, _int, _vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                             _vp, _i64, ctypes.POINTER(_i64), _vp, _i64, ctypes.POINTER(_i64),
+                             ctypes.POINTER(_i64)], _int),
     "fft_tune": ([_i64, _i64, _int, _int, _int, ctypes.c_char_p, _sz], _int),
     "fft_tuned_choice": ([_i64, _int, ctypes.POINTER(_int), ctypes.POINTER(_int),
                           ctypes.POINTER(_int)], _int),
@@ -240,20 +241,24 @@ def fft_batch_destroy(batch: int) -> None:
 WORK_FIELDS = ("cfg", "nunits", "first", "log_m", "phase", "slot", "in_off", "out_off")
 
 
-def fft_batch_work_list(sizes):
+def fft_batch_work_list(sizes, dtype="f16"):
     """The work list of an uneven batch (host only): (items (k, 8) int64 with
     columns WORK_FIELDS, number of phase-0 items, whole-transform offsets,
-    workspace elements)."""
+    list-kernel offsets, workspace elements)."""
     arr = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
-    ni, p0, no, ws = _i64(), _i64(), _i64(), _i64()
-    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, None, 0, ctypes.byref(ni),
-                                    ctypes.byref(p0), None, 0, ctypes.byref(no), ctypes.byref(ws)))
+    ni, p0, no, nl, ws = _i64(), _i64(), _i64(), _i64(), _i64()
+    dt = _dt(dtype)
+    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, dt, None, 0, ctypes.byref(ni),
+                                    ctypes.byref(p0), None, 0, ctypes.byref(no), None, 0,
+                                    ctypes.byref(nl), ctypes.byref(ws)))
     items = np.zeros((ni.value, 8), np.int64)
     offs = np.zeros(max(1, no.value), np.int64)
-    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, items.ctypes.data, ni.value,
+    lst = np.zeros(max(1, nl.value), np.int64)
+    _check(_lib.fft_batch_work_list(arr.ctypes.data, arr.size, dt, items.ctypes.data, ni.value,
                                     ctypes.byref(ni), ctypes.byref(p0), offs.ctypes.data, offs.size,
-                                    ctypes.byref(no), ctypes.byref(ws)))
-    return items, p0.value, offs[:no.value], ws.value
+                                    ctypes.byref(no), lst.ctypes.data, lst.size, ctypes.byref(nl),
+                                    ctypes.byref(ws)))
+    return items, p0.value, offs[:no.value], lst[:nl.value], ws.value
 
 
 def fft_serve_slot_create(dtype, kind, max_items: int, max_transforms: int, max_large: int,

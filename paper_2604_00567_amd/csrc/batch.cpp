@@ -43,8 +43,9 @@ struct fft_batch {
     int cfg_choice[17] = {};                 // per log2 N (single-unit sizes)
     std::shared_ptr<dsfft::DeviceTable> table;
     std::vector<dsfft::HostBatchItem> items;
-    std::vector<int64_t> offs;
+    std::vector<int64_t> offs, big;          // big: offsets for the list kernel
     dsfft::HostBatchItem* d_items = nullptr;
+    int64_t* d_big = nullptr;
     int64_t* d_offs = nullptr;
     unsigned* d_ctl = nullptr;
     void* ws = nullptr;
@@ -54,6 +55,7 @@ struct fft_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t knode[2] = {nullptr, nullptr};
+    hipGraphNode_t bnode = nullptr;           // list kernel (binary16 2^15 transforms)
     const void* cap_in = nullptr;
     void* cap_out = nullptr;
     hipEvent_t last = nullptr;
@@ -69,6 +71,7 @@ fft_batch::~fft_batch() {
     if (graph) (void)hipGraphDestroy(graph);
     if (d_items) (void)hipFree(d_items);
     if (d_offs) (void)hipFree(d_offs);
+    if (d_big) (void)hipFree(d_big);
     if (d_ctl) (void)hipFree(d_ctl);
     if (ws) (void)hipFree(ws);
 }
@@ -96,10 +99,11 @@ static Split split_for(int m) {
 // is made of short items); phase 1 = the row items.  Large transforms take
 // consecutive workspace slices; ws_elems returns their total.
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
-                std::vector<HostBatchItem>& items, std::vector<int64_t>& offs, int64_t& ws_elems,
-                int64_t& phase0) {
+                int big_log, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
+                std::vector<int64_t>& big, int64_t& ws_elems, int64_t& phase0) {
     items.clear();
     offs.clear();
+    big.clear();
     std::vector<HostBatchItem> rows;
     std::vector<std::vector<int64_t>> by_class(19);
     ws_elems = 0;
@@ -109,6 +113,10 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
         while ((int64_t(1) << m) < n[t]) ++m;
         if (m <= kMaxSingleLog) {
             by_class[m].push_back(off[t]);
+            continue;
+        }
+        if (m == big_log) {
+            big.push_back(off[t]);
             continue;
         }
         const Split sp = split_for(m);
@@ -164,8 +172,8 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
 static int build_items(fft_batch* b) {
     if (batch_resident_grid(b->dtype, b->device, &b->resident) != FFT_OK) return FFT_EHIP;
     int64_t ws_elems = 0;
-    build_work(b->n.data(), b->offset.data(), b->count, b->cfg_choice, b->items, b->offs, ws_elems,
-               b->phase0);
+    build_work(b->n.data(), b->offset.data(), b->count, b->cfg_choice, big_log_for(b->dtype),
+               b->items, b->offs, b->big, ws_elems, b->phase0);
     b->ws_bytes = (size_t)ws_elems * elem_bytes(b->dtype);
     return FFT_OK;
 }
@@ -187,12 +195,16 @@ static int upload(fft_batch* b) {
     hipError_t e;
     if (b->d_items) { (void)hipFree(b->d_items); b->d_items = nullptr; }
     if (b->d_offs) { (void)hipFree(b->d_offs); b->d_offs = nullptr; }
+    if (b->d_big) { (void)hipFree(b->d_big); b->d_big = nullptr; }
     if (b->d_ctl) { (void)hipFree(b->d_ctl); b->d_ctl = nullptr; }
     if (b->ws) { (void)hipFree(b->ws); b->ws = nullptr; }
     const size_t ib = std::max<size_t>(1, b->items.size()) * sizeof(HostBatchItem);
     const size_t ob = std::max<size_t>(1, b->offs.size()) * sizeof(int64_t);
     if ((e = hipMalloc(&b->d_items, ib)) != hipSuccess) return hip_error(e, "hipMalloc(items)");
     if ((e = hipMalloc(&b->d_offs, ob)) != hipSuccess) return hip_error(e, "hipMalloc(offsets)");
+    if (!b->big.empty() &&
+        (e = hipMalloc(&b->d_big, b->big.size() * sizeof(int64_t))) != hipSuccess)
+        return hip_error(e, "hipMalloc(list offsets)");
     if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * kQueueWords)) != hipSuccess)
         return hip_error(e, "hipMalloc(control)");
     if (b->ws_bytes && (e = hipMalloc(&b->ws, b->ws_bytes)) != hipSuccess)
@@ -206,6 +218,10 @@ static int upload(fft_batch* b) {
         (e = hipMemcpy(b->d_offs, b->offs.data(), b->offs.size() * sizeof(int64_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_error(e, "hipMemcpy(offsets)");
+    if (!b->big.empty() &&
+        (e = hipMemcpy(b->d_big, b->big.data(), b->big.size() * sizeof(int64_t),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_error(e, "hipMemcpy(list offsets)");
     if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * kQueueWords)) != hipSuccess)
         return hip_error(e, "hipMemset(queue words)");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_error(e, "hipDeviceSynchronize");
@@ -249,11 +265,45 @@ static hipKernelNodeParams phase_params(const fft_batch* b, PhaseArgs& a, int ph
     return kp;
 }
 
-// Builds the graph once: phase 0, then phase 1 (each a persistent kernel).
+// Kernel-node arguments of the list kernel.
+struct ListArgs {
+    const void* in;
+    void* out;
+    const void* lt;
+    const int64_t* offs;
+    int64_t count;
+    void* slots[5];
+    ListArgs(const fft_batch* b, const void* in_, void* out_)
+        : in(in_), out(out_), lt(b->table->ptr), offs(b->d_big), count((int64_t)b->big.size()) {
+        void* p[5] = {&in, &out, &lt, &offs, &count};
+        std::copy(p, p + 5, slots);
+    }
+};
+
+static hipKernelNodeParams list_params(const fft_batch* b, ListArgs& a) {
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void*>(batch_big_func());
+    kp.gridDim = dim3((unsigned)b->big.size());
+    kp.blockDim = dim3(kBigListThreads);
+    kp.sharedMemBytes = (unsigned)batch_big_lds_bytes();
+    kp.kernelParams = a.slots;
+    kp.extra = nullptr;
+    return kp;
+}
+
+// Builds the graph once: the list kernel (if any transforms use it), then
+// phase 0, then phase 1 (each a persistent kernel).
 static int build_graph(fft_batch* b, const void* in, void* out) {
     hipError_t e;
     if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_error(e, "hipGraphCreate");
     hipGraphNode_t prev = nullptr;
+    if (!b->big.empty()) {
+        ListArgs la(b, in, out);
+        hipKernelNodeParams kp = list_params(b, la);
+        if ((e = hipGraphAddKernelNode(&b->bnode, b->graph, nullptr, 0, &kp)) != hipSuccess)
+            return hip_error(e, "hipGraphAddKernelNode(list)");
+        prev = b->bnode;
+    }
     for (int ph = 0; ph < 2; ++ph) {
         PhaseArgs a(b, in, out, ph);
         if (a.nitems == 0) continue;
@@ -270,8 +320,14 @@ static int build_graph(fft_batch* b, const void* in, void* out) {
     return FFT_OK;
 }
 
-// Points both phase nodes at new data buffers.
+// Points the kernel nodes at new data buffers.
 static int retarget(fft_batch* b, const void* in, void* out) {
+    if (b->bnode) {
+        ListArgs la(b, in, out);
+        hipKernelNodeParams kp = list_params(b, la);
+        hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->bnode, &kp);
+        if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(list)");
+    }
     for (int ph = 0; ph < 2; ++ph) {
         if (!b->knode[ph]) continue;
         PhaseArgs a(b, in, out, ph);
@@ -294,7 +350,7 @@ int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s) {
     const size_t bytes = (size_t)b->total * eb;
     if (x != y && x < y + bytes && y < x + bytes)
         return set_error(FFT_EINVAL, "in and out partially overlap");
-    if (b->items.empty()) return FFT_OK;
+    if (b->items.empty() && b->big.empty()) return FFT_OK;
     int rc = FFT_OK;
     if (!b->exec) rc = build_graph(b, in, out);
     else if (b->cap_in != in || b->cap_out != out) rc = retarget(b, in, out);
@@ -391,11 +447,13 @@ int fft_batch_info(const fft_batch* b, int64_t* items, int64_t* grid, size_t* wo
 
 void fft_batch_destroy(fft_batch* b) { delete b; }
 
-int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int64_t item_cap,
-                        int64_t* nitems, int64_t* phase0, int64_t* offs_out, int64_t offs_cap,
-                        int64_t* noffs, int64_t* ws_elems) {
-    if (!n || count < 0 || !nitems || !phase0 || !noffs || !ws_elems)
+int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_t* items_out,
+                        int64_t item_cap, int64_t* nitems, int64_t* phase0, int64_t* offs_out,
+                        int64_t offs_cap, int64_t* noffs, int64_t* list_out, int64_t list_cap,
+                        int64_t* nlist, int64_t* ws_elems) {
+    if (!n || count < 0 || !nitems || !phase0 || !noffs || !nlist || !ws_elems)
         return set_error(FFT_EINVAL, "null argument");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32) return set_error(FFT_EINVAL, "bad dtype");
     std::vector<int64_t> sizes(n, n + count), offset(count);
     int64_t total = 0;
     for (int64_t i = 0; i < count; ++i) {
@@ -406,13 +464,16 @@ int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int
         total += v;
     }
     std::vector<HostBatchItem> items;
-    std::vector<int64_t> offs;
-    build_work(sizes.data(), offset.data(), count, kSmallCfg, items, offs, *ws_elems, *phase0);
+    std::vector<int64_t> offs, big;
+    build_work(sizes.data(), offset.data(), count, kSmallCfg, big_log_for((int)dtype), items, offs,
+               big, *ws_elems, *phase0);
     *nitems = (int64_t)items.size();
     *noffs = (int64_t)offs.size();
-    if (!items_out && !offs_out) return FFT_OK;     // size query
-    if ((int64_t)items.size() > item_cap || (int64_t)offs.size() > offs_cap)
-        return set_error(FFT_EINVAL, "output capacity too small (sizes returned in nitems, noffs)");
+    *nlist = (int64_t)big.size();
+    if (!items_out && !offs_out && !list_out) return FFT_OK;     // size query
+    if ((int64_t)items.size() > item_cap || (int64_t)offs.size() > offs_cap ||
+        (int64_t)big.size() > list_cap)
+        return set_error(FFT_EINVAL, "output capacity too small (sizes returned in nitems, noffs, nlist)");
     for (size_t i = 0; i < items.size(); ++i) {
         const HostBatchItem& it = items[i];
         const int64_t row[8] = {it.cfg, it.nunits, it.first, it.log_m, it.phase, it.slot,
@@ -420,6 +481,7 @@ int fft_batch_work_list(const int64_t* n, int64_t count, int64_t* items_out, int
         std::copy(row, row + 8, items_out + 8 * i);
     }
     std::copy(offs.begin(), offs.end(), offs_out);
+    std::copy(big.begin(), big.end(), list_out);
     return FFT_OK;
 }
 

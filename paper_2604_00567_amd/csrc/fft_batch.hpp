@@ -134,6 +134,39 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
     }
 }
 
+// Whole transforms too large for the batch kernel's LDS (binary16, 2^15
+// points: 128 KiB) run in a kernel of their own, one transform per workgroup,
+// with unit u of the launch at element offset offs[u].
+struct ListGeo {
+    const int64_t* offs;
+    int64_t ublk, units;
+    int lane_id;
+    template <int LOG_NU, int MODE>
+    __device__ __forceinline__ UnitGeom get(int ul) const {
+        UnitGeom u;
+        u.in_stride = u.out_stride = 1;
+        u.q0 = 0;
+        u.log_lb = 0;
+        u.base_in = u.base_out = (ublk + ul < units) ? offs[ublk + ul] : 0;
+        return u;
+    }
+    __device__ __forceinline__ bool active(int ul) const { return ublk + ul < units; }
+    __device__ __forceinline__ int tid() const { return lane_id; }
+    __device__ __forceinline__ int64_t block_first(int) const { return 0; }
+    __device__ __forceinline__ int64_t block_units(int) const { return 0; }
+};
+
+template <class E, int LOG_NU, int LOG_E, int LR0, int LR1, int LR2>
+__global__ void __launch_bounds__(1 << (LOG_NU - LOG_E))
+fft_list_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
+                const int64_t* __restrict__ offs, int64_t count) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+    E* lds = reinterpret_cast<E*>(lds_raw);
+    E v[1 << LOG_E];
+    const ListGeo gp{offs, (int64_t)blockIdx.x, count, (int)threadIdx.x};
+    unit_pass<E, LOG_NU, LOG_E, 1, 1, MODE_SMALL, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, in, out, gp);
+}
+
 // Items first .. first + nitems - 1 of one phase.  q[0] is the phase's queue
 // head and q[1] counts the workgroups that have left the loop; both are zero
 // at launch, and the last workgroup to leave sets them back to zero for the

@@ -17,6 +17,26 @@ const void* batch_kernel_func(int dtype) {
     return dtype == 0 ? (const void*)&fft_batch_kernel<uint32_t> : (const void*)&fft_batch_kernel<f2_t>;
 }
 
+// The binary16 2^15-point list kernel: 1024 threads (32 elements each),
+// radix 2^5 passes, one transform per workgroup.
+#define DSFFT_BIG_KERNEL fft_list_kernel<uint32_t, kBigListLog, 5, 5, 5, 5>
+
+size_t batch_big_lds_bytes() {
+    return (size_t)PassPlan<kBigListLog, 5, 5, 5, 0>::region() * sizeof(uint32_t);
+}
+
+const void* batch_big_func() { return (const void*)&DSFFT_BIG_KERNEL; }
+
+hipError_t launch_batch_big(const void* in, void* out, const void* lt, const int64_t* offs,
+                            int64_t count, hipStream_t s) {
+    static_assert(kBigListThreads == (1 << (kBigListLog - 5)), "list kernel geometry");
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(DSFFT_BIG_KERNEL, dim3((unsigned)count), dim3(kBigListThreads),
+                       batch_big_lds_bytes(), s, (const uint32_t*)in, (uint32_t*)out, (const TwH*)lt,
+                       offs, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch(int dtype, const void* in, void* out, void* ws, const void* lt,
                         const void* items, const int64_t* offs, int first, int nitems,
                         unsigned* q, int grid, hipStream_t s) {

@@ -30,7 +30,7 @@ struct fft_serve_slot {
     int cfg_choice[17] = {};
     hipEvent_t done = nullptr;
     bool launched = false;
-    std::vector<int64_t> tn, toff, offs;
+    std::vector<int64_t> tn, toff, offs, big;
     std::vector<dsfft::HostBatchItem> items;
     ~fft_serve_slot();
 };
@@ -119,18 +119,27 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
         if (v >= (int64_t(1) << 15)) nlarge += batch[r];
     }
     int64_t ws_elems = 0, phase0 = 0;
-    build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice, s->items,
-               s->offs, ws_elems, phase0);
-    if ((int64_t)s->items.size() > s->item_cap || (int64_t)s->offs.size() > s->offs_cap ||
-        nlarge > s->slot_cap || (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
+    build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice,
+               big_log_for(s->dtype), s->items, s->offs, s->big, ws_elems, phase0);
+    if ((int64_t)s->items.size() > s->item_cap ||
+        (int64_t)(s->offs.size() + s->big.size()) > s->offs_cap || nlarge > s->slot_cap ||
+        (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
         return set_error(FFT_ENOMEM, "step exceeds the slot's capacity");
-    if (s->items.empty()) return FFT_OK;
+    if (s->items.empty() && s->big.empty()) return FFT_OK;
+    // staging layout: work items, single-unit offsets, list-kernel offsets
     const size_t ib = sizeof(HostBatchItem) * s->items.size();   // a multiple of 8
+    const size_t ob = sizeof(int64_t) * s->offs.size();
+    const size_t bb = sizeof(int64_t) * s->big.size();
     std::memcpy(s->h_stage, s->items.data(), ib);
-    std::memcpy(s->h_stage + ib, s->offs.data(), sizeof(int64_t) * s->offs.size());
-    if ((e = hipMemcpyAsync(s->d_stage, s->h_stage, ib + sizeof(int64_t) * s->offs.size(),
-                            hipMemcpyHostToDevice, st)) != hipSuccess)
+    std::memcpy(s->h_stage + ib, s->offs.data(), ob);
+    std::memcpy(s->h_stage + ib + ob, s->big.data(), bb);
+    if ((e = hipMemcpyAsync(s->d_stage, s->h_stage, ib + ob + bb, hipMemcpyHostToDevice, st)) !=
+        hipSuccess)
         return hip_error(e, "hipMemcpyAsync(work list)");
+    if (!s->big.empty() &&
+        (e = launch_batch_big(data, data, s->table->ptr, (const int64_t*)(s->d_stage + ib + ob),
+                              (int64_t)s->big.size(), st)) != hipSuccess)
+        return hip_error(e, "launch(list)");
     const int64_t n1 = (int64_t)s->items.size() - phase0;
     const int grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(phase0, s->resident));
     const int grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, s->resident));

@@ -21,12 +21,15 @@ def classify(it):
     return "small"
 
 
-def check(sizes):
+def check(sizes, dtype="f16"):
     sizes = np.asarray(sizes, np.int64)
-    items, phase0, offs, ws = binding.fft_batch_work_list(sizes)
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list(sizes, dtype)
     assert np.all(items[:phase0, F["phase"]] == 0) and np.all(items[phase0:, F["phase"]] == 1)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    large = sizes >= (1 << 15)
+    # binary16 2^15 transforms run whole in the list kernel; larger ones split
+    listed = (sizes == (1 << 15)) if dtype == "f16" else np.zeros(sizes.shape, bool)
+    assert sorted(int(v) for v in lst) == sorted(int(v) for v in starts[listed])
+    large = (sizes >= (1 << 15)) & ~listed
     assert ws == int(sizes[large].sum())
 
     # single-unit transforms: each start exactly once, with the class's config
@@ -39,7 +42,7 @@ def check(sizes):
                 small_starts.append(o)
                 t = int(np.searchsorted(starts, o))
                 assert starts[t] == o and sizes[t] == 1 << ln
-    assert sorted(small_starts) == sorted(int(s) for s in starts[~large])
+    assert sorted(small_starts) == sorted(int(s) for s in starts[sizes < (1 << 15)])
 
     # large transforms: columns and rows each covered once; waits point back
     by_slot = {}
@@ -90,9 +93,10 @@ def check(sizes):
     return items, by_slot, last_col
 
 
-def test_work_list_mixed_sizes():
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_work_list_mixed_sizes(dtype):
     sizes = inputs.uneven_sizes(4096, seed=4, log_lo=1, log_hi=18)
-    check(sizes)
+    check(sizes, dtype)
 
 
 def test_work_list_order():
@@ -107,11 +111,15 @@ def test_work_list_order():
 
 
 def test_work_list_only_small_or_only_large():
-    items, phase0, offs, ws = binding.fft_batch_work_list([64] * 100)
-    assert phase0 == len(items) and ws == 0 and len(offs) == 100
-    items, phase0, offs, ws = binding.fft_batch_work_list([1 << 16] * 3)
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([64] * 100)
+    assert phase0 == len(items) and ws == 0 and len(offs) == 100 and len(lst) == 0
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 16] * 3)
     assert 0 < phase0 < len(items) and ws == 3 << 16 and len(offs) == 0
     check([1 << 16] * 3)
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 15] * 5, "f16")
+    assert len(items) == 0 and ws == 0 and list(lst) == [i << 15 for i in range(5)]
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 15] * 5, "f32")
+    assert len(items) > 0 and ws == 5 << 15 and len(lst) == 0
 
 
 def test_work_list_rejects_bad_sizes():
