@@ -38,6 +38,9 @@ using BatchItem = HostBatchItem;
 
 // Unit geometry of one work item.
 struct BatchGeo {
+    // no twiddle prefetch: the kernel's registers are the largest over all its
+    // configurations, and prefetching raises that maximum into spills
+    static constexpr bool kTwiddlePrefetch = false;
     const int64_t* offs;
     BatchItem it;
     int lane_id;       // threadIdx.x, made opaque per configuration (batch_unit)
@@ -138,6 +141,7 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
 // points: 128 KiB) run in a kernel of their own, one transform per workgroup,
 // with unit u of the launch at element offset offs[u].
 struct ListGeo {
+    static constexpr bool kTwiddlePrefetch = false;
     const int64_t* offs;
     int64_t ublk, units;
     int lane_id;

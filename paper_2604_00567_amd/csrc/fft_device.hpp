@@ -305,7 +305,10 @@ __device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __
 // Where the units of one workgroup live: a regular launch takes UPW
 // consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
 // units of one work item (BatchGeo, in fft_batch.hpp).
-struct GridGeo {
+template <bool TWPF>
+struct GridGeoT {
+    // the next pass's twiddles are loaded a pass ahead (twiddle_prefetch)
+    static constexpr bool kTwiddlePrefetch = TWPF;
     int64_t ublk, units;
     int log_m;
     int lane_id;       // threadIdx.x (opaque per block in the persistent loop)
@@ -321,6 +324,7 @@ struct GridGeo {
         return units - ublk < upw ? units - ublk : upw;
     }
 };
+using GridGeo = GridGeoT<false>;
 
 // Lanes and units.  A lane holds groups of UPL units (units per lane): the
 // same group positions g + G u of units ul0 .. ul0 + UPL - 1, so each twiddle
@@ -368,12 +372,69 @@ __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
     }
 }
 
+// Twiddles of register pass P for this lane's groups: tw[u * R + c] is the
+// entry of butterfly index c (1 <= c < R) of group g + G u.  Entries depend on
+// the lane's position only, not on data.
+template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P>
+__device__ __forceinline__ void pass_twiddles(typename TwOf<E>::type* tw,
+                                              const typename TwOf<E>::type* __restrict__ lt,
+                                              const UnitGeom& geo0, int g) {
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+    constexpr int NU = 1 << LOG_NU;
+    constexpr int EL = 1 << LOG_E;
+    constexpr int G = NU / EL;
+    constexpr int R = 1 << PP::lr(P);
+    constexpr int L0 = 1 << PP::log_l0(P);
+    constexpr int LOGM = PP::log_m(P);
+    constexpr int GPL = EL / R;
+#pragma unroll
+    for (int u = 0; u < GPL; ++u) {
+        const int q = (g + G * u) >> LOGM;    // column within the unit
+        if constexpr (P == 0 && MODE != MODE_ROWS) {
+#pragma unroll
+            for (int c = 1; c < R; ++c) tw[u * R + c] = lt[c];
+        } else {
+            const int qg = geo0.q0 + (q << geo0.log_lb);
+            const int lg0 = L0 << geo0.log_lb;
+#pragma unroll
+            for (int c = 1; c < R; ++c) tw[u * R + c] = lt[qg + lg0 * c];
+        }
+    }
+}
+
+// Twiddle prefetch (configurations with PIPE = 2): whole-transform units load
+// the twiddles of pass P + 1 at the start of pass P, so that their latency
+// overlaps the data loads (pass 0) or the exchange; the table misses the
+// vector L1 cache, and loaded at the point of use each pass waits for L2.  It
+// costs the VGPRs that hold them, so it is a per-configuration choice for the
+// tuner; it applies where each pass's set fits in 64 VGPRs per lane.
+template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE>
+constexpr bool twiddle_prefetch() {
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+    if (MODE != MODE_SMALL || LANE || PP::NP < 2) return false;
+    for (int p = 1; p < PP::NP; ++p) {
+        const int regs = ((1 << LOG_E) >> PP::lr(p)) * ((1 << PP::lr(p)) - 1) *
+                         (int)(sizeof(typename TwOf<E>::type) / 4);
+        if (regs > 64) return false;
+    }
+    return true;
+}
+
+// Marks a prefetched twiddle as needed here: the loads that fill it must have
+// returned by this point (and the compiler cannot move them after it).
+__device__ __forceinline__ void pin_twiddle(TwH& t) { asm volatile("" : "+v"(t.w), "+v"(t.ts)); }
+__device__ __forceinline__ void pin_twiddle(TwF& t) {
+    asm volatile("" : "+v"(t.sm), "+v"(t.m), "+v"(t.t), "+v"(t.mask));
+}
+
 // One register pass P of the unit schedule: gather (global or LDS), twiddles,
-// LR radix-2 stages per group, scatter (LDS or global).
+// LR radix-2 stages per group, scatter (LDS or global).  twp: this pass's
+// twiddles when the previous pass loaded them (twiddle_prefetch).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PRE, int P, class Geo>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
-                                          const E* in, E* out, const Geo& gp) {
+                                          const E* in, E* out, const Geo& gp,
+                                          const typename TwOf<E>::type* twp = nullptr) {
     using TW = typename TwOf<E>::type;
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NP = PP::NP;
@@ -400,6 +461,17 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         const int g = lane_map ? (((g0 & 15) << 2) | (g0 >> 4)) : g0;
         // twiddle offsets of the row kernel (the same for every unit of a lane)
         const UnitGeom geo0 = gp.template get<LOG_NU, MODE>(ul0);
+
+        // ---- the next pass's twiddles (whole-transform units), issued ahead of
+        // this pass's gather; the empty asm keeps them ahead of it
+        constexpr bool PF = Geo::kTwiddlePrefetch && !PRE &&
+                            twiddle_prefetch<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE>();
+        constexpr int NEXT_TW = (PF && P + 1 < NP) ? (EL >> PP::lr(P + 1)) << PP::lr(P + 1) : 1;
+        TW twn[NEXT_TW];
+        if constexpr (PF && P + 1 < NP) {
+            pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P + 1>(twn, lt, geo0, g);
+            asm volatile("" ::: "memory");
+        }
 
         // ---- gather
         if constexpr (P == 0 && STG) {
@@ -440,22 +512,23 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
+        TW tw[GPL * R];
+        if constexpr (PF && P > 0) {
+#pragma unroll
+            for (int i = 0; i < GPL * R; ++i) tw[i] = twp[i];
+        } else {
+            pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g);
+        }
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
-            const int gam = g + G * u;
-            const int q = gam >> LOGM;            // column within the unit
-            TW tw[R];
-            if constexpr (P == 0 && MODE != MODE_ROWS) {
 #pragma unroll
-                for (int c = 1; c < R; ++c) tw[c] = lt[c];
-            } else {
-                const int qg = geo0.q0 + (q << geo0.log_lb);
-                const int lg0 = L0 << geo0.log_lb;
+            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw + u * R);
+        }
+        if constexpr (PF && P + 1 < NP) {
+            // entries c >= 1 of each group are the loaded ones
 #pragma unroll
-                for (int c = 1; c < R; ++c) tw[c] = lt[qg + lg0 * c];
-            }
-#pragma unroll
-            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw);
+            for (int i = 0; i < NEXT_TW; ++i)
+                if (i & ((1 << PP::lr(P + 1)) - 1)) pin_twiddle(twn[i]);
         }
 
         // ---- scatter
@@ -541,7 +614,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
             }
         }
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PRE, P + 1>(v, lds, lt, in,
-                                                                                           out, gp);
+                                                                                           out, gp, twn);
     }
 }
 
@@ -586,9 +659,10 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
     static_assert(STG == 0 || MODE != MODE_COLS, "staging needs contiguous units");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
-    static_assert(PIPE == 0 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
+    static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
+    static_assert(PIPE != 2 || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
     E v[UPL << LOG_E];
-    if constexpr (PIPE) {
+    if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
         // in two register sets used alternately (a and b), so the next block's
         // HBM reads are in flight while the current block is computed and no
@@ -626,7 +700,7 @@ __device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
             blk += step;
         }
     } else {
-        const GridGeo gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
+        const GridGeoT<PIPE == 2> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

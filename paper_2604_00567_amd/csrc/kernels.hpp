@@ -21,7 +21,8 @@ struct KernelCfg {
     int lr[3];      // register-pass radices (log2; 0 = absent)
     int staged;     // 1: block copied through LDS with 16-byte accesses
     int lane_tail;  // 1: the last two stages run across lanes (permlane swaps)
-    int pipelined;  // 1: persistent workgroups prefetch the next block into registers
+    int pipelined;  // 1: persistent workgroups prefetch the next block into registers;
+                    // 2: each pass loads the next pass's twiddles
     int threads;    // workgroup size
     size_t lds_bytes;
     LaunchFn launch;

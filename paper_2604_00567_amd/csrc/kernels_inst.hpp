@@ -7,11 +7,11 @@
 namespace dsfft {
 
 // The kernel entry for a configuration: the pipelined entry (with its
-// occupancy attribute) only where PIPE is set.
+// occupancy attribute) only where PIPE = 1.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
 static constexpr auto kernel_entry() {
-    if constexpr (PIPE)
+    if constexpr (PIPE == 1)
         return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
     else
         return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
@@ -28,7 +28,7 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
     auto kern = kernel_entry<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
     int64_t grid = (units + UPW - 1) / UPW;
     if (grid <= 0) return hipSuccess;
-    if (PIPE) {
+    if (PIPE == 1) {
         // persistent grid: the workgroups that fit on the device at once
         static int resident = 0;
         if (!resident) {
