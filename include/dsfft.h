@@ -182,8 +182,9 @@ int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* ro
  * schedule.  The first kernel runs every column item and every
  * whole-transform item, the second every row item; the launch boundary
  * orders each transform's row items after its column items.  Binary16
- * transforms of 2^15 points (128 KiB, one workgroup's LDS) run whole in a
- * kernel of their own, over a list of their offsets, before the two.  The
+ * transforms of 2^16 and 2^15 points (256 and 128 KiB, more than the batch
+ * kernel's LDS) run whole in two list kernels of their own, one transform per
+ * 1024-thread workgroup, over lists of their offsets, before the two.  The
  * launches form one HIP graph built at the first execute and replayed by
  * every execute (the kernels leave their work-queue counters at zero for the
  * next replay); new data pointers are set on the graph's kernel nodes.  The
@@ -227,7 +228,8 @@ void fft_batch_destroy(fft_batch* batch);
  * items write, and row items read, the workspace).  The first *phase0 items
  * are phase 0.  offs_out receives the transform offsets of the
  * whole-transform items, list_out those of the transforms run by the list
- * kernel.  nitems, phase0, noffs, nlist and ws_elems (workspace elements) are
+ * kernels (binary16 2^16-point transforms first, then 2^15-point ones, each
+ * in input order).  nitems, phase0, noffs, nlist and ws_elems (workspace elements) are
  * always set; with all output pointers NULL the call only reports the sizes;
  * FFT_EINVAL when a capacity is too small. */
 int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_t* items_out,
@@ -240,9 +242,10 @@ int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_
  * uneven-batch kernels over the requests admitted in one scheduling step of a
  * continuous-batching server (the same butterflies and tables as every other
  * entry point).  Capacities: max_items work items, max_transforms
- * whole transforms (work items and list kernel together), max_large
- * transforms of 2^15 points or more, and
- * ws_bytes of workspace for them.  Returns NULL on error.
+ * whole transforms (work items and list kernels together), max_large
+ * transforms that take the column/row split (binary16 2^17 and 2^18 points,
+ * binary32 2^15 and up), and ws_bytes of workspace for them.  Returns NULL on
+ * error.
  */
 fft_serve_slot* fft_serve_slot_create(fft_dtype dtype, fft_table_kind kind, int64_t max_items,
                                       int64_t max_transforms, int max_large, size_t ws_bytes);

@@ -127,9 +127,14 @@ std::string describe(const KernelCfg* k) {
     return d;
 }
 
-// Largest single-kernel size per dtype (a binary16 transform of 2^15 points,
-// 128 KiB, still fits one workgroup's LDS), and the two-pass split.
-static int small_limit(int dtype) { return dtype == DT_F16 ? 15 : 14; }
+// Largest single-kernel size per dtype: the largest whole-transform
+// configuration that fits (binary16 2^16 points, whose exchanges run in two
+// rounds through LDS; binary32 2^14); beyond it, the two-pass split.
+static int small_limit(int dtype) {
+    int m = 20;
+    while (m > 0 && count_kernels(dtype, MODE_SMALL, m) == 0) --m;
+    return m;
+}
 
 int choose_schedule(fft_plan* p, const int* variants) {
     const int m = p->log_n;

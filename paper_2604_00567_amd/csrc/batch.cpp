@@ -43,9 +43,10 @@ struct fft_batch {
     int cfg_choice[17] = {};                 // per log2 N (single-unit sizes)
     std::shared_ptr<dsfft::DeviceTable> table;
     std::vector<dsfft::HostBatchItem> items;
-    std::vector<int64_t> offs, big;          // big: offsets for the list kernel
+    std::vector<int64_t> offs, lists;        // lists: offsets for the list kernels
+    int64_t nlist[dsfft::kNumLists] = {};
     dsfft::HostBatchItem* d_items = nullptr;
-    int64_t* d_big = nullptr;
+    int64_t* d_lists = nullptr;
     int64_t* d_offs = nullptr;
     unsigned* d_ctl = nullptr;
     void* ws = nullptr;
@@ -55,7 +56,7 @@ struct fft_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t knode[2] = {nullptr, nullptr};
-    hipGraphNode_t bnode = nullptr;           // list kernel (binary16 2^15 transforms)
+    hipGraphNode_t lnode[dsfft::kNumLists] = {};   // list kernels (binary16 2^16, 2^15)
     const void* cap_in = nullptr;
     void* cap_out = nullptr;
     hipEvent_t last = nullptr;
@@ -71,7 +72,7 @@ fft_batch::~fft_batch() {
     if (graph) (void)hipGraphDestroy(graph);
     if (d_items) (void)hipFree(d_items);
     if (d_offs) (void)hipFree(d_offs);
-    if (d_big) (void)hipFree(d_big);
+    if (d_lists) (void)hipFree(d_lists);
     if (d_ctl) (void)hipFree(d_ctl);
     if (ws) (void)hipFree(ws);
 }
@@ -99,11 +100,12 @@ static Split split_for(int m) {
 // is made of short items); phase 1 = the row items.  Large transforms take
 // consecutive workspace slices; ws_elems returns their total.
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
-                int big_log, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
-                std::vector<int64_t>& big, int64_t& ws_elems, int64_t& phase0) {
+                int nlists, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
+                std::vector<int64_t>& lists, int64_t* nlist, int64_t& ws_elems, int64_t& phase0) {
     items.clear();
     offs.clear();
-    big.clear();
+    lists.clear();
+    std::vector<int64_t> per_list[kNumLists];
     std::vector<HostBatchItem> rows;
     std::vector<std::vector<int64_t>> by_class(19);
     ws_elems = 0;
@@ -115,8 +117,11 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
             by_class[m].push_back(off[t]);
             continue;
         }
-        if (m == big_log) {
-            big.push_back(off[t]);
+        int li = -1;
+        for (int i = 0; i < nlists; ++i)
+            if (m == kListLog[i]) li = i;
+        if (li >= 0) {
+            per_list[li].push_back(off[t]);
             continue;
         }
         const Split sp = split_for(m);
@@ -167,13 +172,17 @@ void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* 
     }
     phase0 = (int64_t)items.size();
     items.insert(items.end(), rows.begin(), rows.end());
+    for (int i = 0; i < kNumLists; ++i) {
+        nlist[i] = (int64_t)per_list[i].size();
+        lists.insert(lists.end(), per_list[i].begin(), per_list[i].end());
+    }
 }
 
 static int build_items(fft_batch* b) {
     if (batch_resident_grid(b->dtype, b->device, &b->resident) != FFT_OK) return FFT_EHIP;
     int64_t ws_elems = 0;
-    build_work(b->n.data(), b->offset.data(), b->count, b->cfg_choice, big_log_for(b->dtype),
-               b->items, b->offs, b->big, ws_elems, b->phase0);
+    build_work(b->n.data(), b->offset.data(), b->count, b->cfg_choice, lists_for(b->dtype),
+               b->items, b->offs, b->lists, b->nlist, ws_elems, b->phase0);
     b->ws_bytes = (size_t)ws_elems * elem_bytes(b->dtype);
     return FFT_OK;
 }
@@ -195,15 +204,15 @@ static int upload(fft_batch* b) {
     hipError_t e;
     if (b->d_items) { (void)hipFree(b->d_items); b->d_items = nullptr; }
     if (b->d_offs) { (void)hipFree(b->d_offs); b->d_offs = nullptr; }
-    if (b->d_big) { (void)hipFree(b->d_big); b->d_big = nullptr; }
+    if (b->d_lists) { (void)hipFree(b->d_lists); b->d_lists = nullptr; }
     if (b->d_ctl) { (void)hipFree(b->d_ctl); b->d_ctl = nullptr; }
     if (b->ws) { (void)hipFree(b->ws); b->ws = nullptr; }
     const size_t ib = std::max<size_t>(1, b->items.size()) * sizeof(HostBatchItem);
     const size_t ob = std::max<size_t>(1, b->offs.size()) * sizeof(int64_t);
     if ((e = hipMalloc(&b->d_items, ib)) != hipSuccess) return hip_error(e, "hipMalloc(items)");
     if ((e = hipMalloc(&b->d_offs, ob)) != hipSuccess) return hip_error(e, "hipMalloc(offsets)");
-    if (!b->big.empty() &&
-        (e = hipMalloc(&b->d_big, b->big.size() * sizeof(int64_t))) != hipSuccess)
+    if (!b->lists.empty() &&
+        (e = hipMalloc(&b->d_lists, b->lists.size() * sizeof(int64_t))) != hipSuccess)
         return hip_error(e, "hipMalloc(list offsets)");
     if ((e = hipMalloc(&b->d_ctl, sizeof(unsigned) * kQueueWords)) != hipSuccess)
         return hip_error(e, "hipMalloc(control)");
@@ -218,8 +227,8 @@ static int upload(fft_batch* b) {
         (e = hipMemcpy(b->d_offs, b->offs.data(), b->offs.size() * sizeof(int64_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_error(e, "hipMemcpy(offsets)");
-    if (!b->big.empty() &&
-        (e = hipMemcpy(b->d_big, b->big.data(), b->big.size() * sizeof(int64_t),
+    if (!b->lists.empty() &&
+        (e = hipMemcpy(b->d_lists, b->lists.data(), b->lists.size() * sizeof(int64_t),
                        hipMemcpyHostToDevice)) != hipSuccess)
         return hip_error(e, "hipMemcpy(list offsets)");
     if ((e = hipMemset(b->d_ctl, 0, sizeof(unsigned) * kQueueWords)) != hipSuccess)
@@ -265,7 +274,7 @@ static hipKernelNodeParams phase_params(const fft_batch* b, PhaseArgs& a, int ph
     return kp;
 }
 
-// Kernel-node arguments of the list kernel.
+// Kernel-node arguments of list kernel `list`.
 struct ListArgs {
     const void* in;
     void* out;
@@ -273,36 +282,39 @@ struct ListArgs {
     const int64_t* offs;
     int64_t count;
     void* slots[5];
-    ListArgs(const fft_batch* b, const void* in_, void* out_)
-        : in(in_), out(out_), lt(b->table->ptr), offs(b->d_big), count((int64_t)b->big.size()) {
+    ListArgs(const fft_batch* b, const void* in_, void* out_, int list)
+        : in(in_), out(out_), lt(b->table->ptr),
+          offs(b->d_lists + (list == 0 ? 0 : b->nlist[0])), count(b->nlist[list]) {
         void* p[5] = {&in, &out, &lt, &offs, &count};
         std::copy(p, p + 5, slots);
     }
 };
 
-static hipKernelNodeParams list_params(const fft_batch* b, ListArgs& a) {
+static hipKernelNodeParams list_params(const fft_batch* b, ListArgs& a, int list) {
     hipKernelNodeParams kp{};
-    kp.func = const_cast<void*>(batch_big_func());
-    kp.gridDim = dim3((unsigned)b->big.size());
-    kp.blockDim = dim3(kBigListThreads);
-    kp.sharedMemBytes = (unsigned)batch_big_lds_bytes();
+    kp.func = const_cast<void*>(batch_list_func(list));
+    kp.gridDim = dim3((unsigned)b->nlist[list]);
+    kp.blockDim = dim3(kListThreads);
+    kp.sharedMemBytes = (unsigned)batch_list_lds_bytes(list);
     kp.kernelParams = a.slots;
     kp.extra = nullptr;
     return kp;
 }
 
-// Builds the graph once: the list kernel (if any transforms use it), then
+// Builds the graph once: the list kernels (those with transforms), then
 // phase 0, then phase 1 (each a persistent kernel).
 static int build_graph(fft_batch* b, const void* in, void* out) {
     hipError_t e;
     if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_error(e, "hipGraphCreate");
     hipGraphNode_t prev = nullptr;
-    if (!b->big.empty()) {
-        ListArgs la(b, in, out);
-        hipKernelNodeParams kp = list_params(b, la);
-        if ((e = hipGraphAddKernelNode(&b->bnode, b->graph, nullptr, 0, &kp)) != hipSuccess)
+    for (int i = 0; i < kNumLists; ++i) {
+        if (b->nlist[i] == 0) continue;
+        ListArgs la(b, in, out, i);
+        hipKernelNodeParams kp = list_params(b, la, i);
+        if ((e = hipGraphAddKernelNode(&b->lnode[i], b->graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                       &kp)) != hipSuccess)
             return hip_error(e, "hipGraphAddKernelNode(list)");
-        prev = b->bnode;
+        prev = b->lnode[i];
     }
     for (int ph = 0; ph < 2; ++ph) {
         PhaseArgs a(b, in, out, ph);
@@ -322,10 +334,11 @@ static int build_graph(fft_batch* b, const void* in, void* out) {
 
 // Points the kernel nodes at new data buffers.
 static int retarget(fft_batch* b, const void* in, void* out) {
-    if (b->bnode) {
-        ListArgs la(b, in, out);
-        hipKernelNodeParams kp = list_params(b, la);
-        hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->bnode, &kp);
+    for (int i = 0; i < kNumLists; ++i) {
+        if (!b->lnode[i]) continue;
+        ListArgs la(b, in, out, i);
+        hipKernelNodeParams kp = list_params(b, la, i);
+        hipError_t e = hipGraphExecKernelNodeSetParams(b->exec, b->lnode[i], &kp);
         if (e != hipSuccess) return hip_error(e, "hipGraphExecKernelNodeSetParams(list)");
     }
     for (int ph = 0; ph < 2; ++ph) {
@@ -350,7 +363,7 @@ int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s) {
     const size_t bytes = (size_t)b->total * eb;
     if (x != y && x < y + bytes && y < x + bytes)
         return set_error(FFT_EINVAL, "in and out partially overlap");
-    if (b->items.empty() && b->big.empty()) return FFT_OK;
+    if (b->items.empty() && b->lists.empty()) return FFT_OK;
     int rc = FFT_OK;
     if (!b->exec) rc = build_graph(b, in, out);
     else if (b->cap_in != in || b->cap_out != out) rc = retarget(b, in, out);
@@ -464,15 +477,16 @@ int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_
         total += v;
     }
     std::vector<HostBatchItem> items;
-    std::vector<int64_t> offs, big;
-    build_work(sizes.data(), offset.data(), count, kSmallCfg, big_log_for((int)dtype), items, offs,
-               big, *ws_elems, *phase0);
+    std::vector<int64_t> offs, lists;
+    int64_t per[kNumLists] = {};
+    build_work(sizes.data(), offset.data(), count, kSmallCfg, lists_for((int)dtype), items, offs,
+               lists, per, *ws_elems, *phase0);
     *nitems = (int64_t)items.size();
     *noffs = (int64_t)offs.size();
-    *nlist = (int64_t)big.size();
+    *nlist = (int64_t)lists.size();
     if (!items_out && !offs_out && !list_out) return FFT_OK;     // size query
     if ((int64_t)items.size() > item_cap || (int64_t)offs.size() > offs_cap ||
-        (int64_t)big.size() > list_cap)
+        (int64_t)lists.size() > list_cap)
         return set_error(FFT_EINVAL, "output capacity too small (sizes returned in nitems, noffs, nlist)");
     for (size_t i = 0; i < items.size(); ++i) {
         const HostBatchItem& it = items[i];
@@ -481,7 +495,7 @@ int fft_batch_work_list(const int64_t* n, int64_t count, fft_dtype dtype, int64_
         std::copy(row, row + 8, items_out + 8 * i);
     }
     std::copy(offs.begin(), offs.end(), offs_out);
-    std::copy(big.begin(), big.end(), list_out);
+    std::copy(lists.begin(), lists.end(), list_out);
     return FFT_OK;
 }
 

@@ -28,32 +28,38 @@ enum HostBatchCfg {
 
 constexpr int kHostBatchThreads = 512;
 
-// Binary16 transforms of 2^15 points (too large for the batch kernel's LDS)
-// run in a kernel of their own over a list of transform offsets.
-constexpr int kBigListLog = 15;
-constexpr int kBigListThreads = 1024;
-
 constexpr int kMaxSingleLog = 14;      // sizes up to 2^14 run as whole-transform items
+
+// Binary16 transforms of 2^16 and 2^15 points (too large for the batch
+// kernel's LDS) run whole in list kernels of their own, one transform per
+// 1024-thread workgroup, over lists of transform offsets: list 0 holds the
+// 2^16-point transforms, list 1 the 2^15-point ones.
+constexpr int kNumLists = 2;
+constexpr int kListLog[kNumLists] = {16, 15};
+constexpr int kListThreads = 1024;
+// Lists a dtype uses (binary16 both, binary32 none) and the largest size it
+// runs whole; larger transforms take the column/row split (and a workspace).
+inline int lists_for(int dtype) { return dtype == 0 ? kNumLists : 0; }
+inline int max_whole_log(int dtype) { return dtype == 0 ? kListLog[0] : kMaxSingleLog; }
 extern const int kSmallCfg[kMaxSingleLog + 1];   // their configuration per log2 N (1..14)
 int cfg_upw(int cfg);                  // units per workgroup of a configuration
 
 // Work list for transforms of sizes n[t] at element offsets off[t] (batch.cpp):
 // phase-0 items (column items, then single-unit items) come first, `phase0`
-// of them, then the phase-1 row items.  With big_log > 0, transforms of
-// 2^big_log points go to `big` (offsets for the list kernel) instead.
+// of them, then the phase-1 row items.  With nlists > 0, transforms of
+// 2^kListLog[i] points (i < nlists) go to the list kernels instead: `lists`
+// holds list 0's offsets, then list 1's, nlist[i] of each.
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
-                int big_log, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
-                std::vector<int64_t>& big, int64_t& ws_elems, int64_t& phase0);
-// big_log for a dtype: binary16 2^15 transforms use the list kernel.
-inline int big_log_for(int dtype) { return dtype == 0 ? kBigListLog : 0; }
+                int nlists, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
+                std::vector<int64_t>& lists, int64_t* nlist, int64_t& ws_elems, int64_t& phase0);
 int batch_resident_grid(int dtype, int device, int* out);
 
 size_t batch_lds_bytes(int dtype);
 const void* batch_kernel_func(int dtype);
-size_t batch_big_lds_bytes();
-const void* batch_big_func();
-hipError_t launch_batch_big(const void* in, void* out, const void* lt, const int64_t* offs,
-                            int64_t count, hipStream_t s);
+size_t batch_list_lds_bytes(int list);
+const void* batch_list_func(int list);
+hipError_t launch_batch_list(int list, const void* in, void* out, const void* lt, const int64_t* offs,
+                             int64_t count, hipStream_t s);
 
 // Queue words per batch or serving slot: (head, workgroups done) for each of
 // the two phases; zero when allocated, and left zero by every launch.

@@ -137,8 +137,8 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
     }
 }
 
-// Whole transforms too large for the batch kernel's LDS (binary16, 2^15
-// points: 128 KiB) run in a kernel of their own, one transform per workgroup,
+// Whole transforms too large for the batch kernel's LDS (binary16, 2^15 and
+// 2^16 points) run in a kernel of their own, one transform per workgroup,
 // with unit u of the launch at element offset offs[u].
 struct ListGeo {
     static constexpr bool kTwiddlePrefetch = false;

@@ -162,7 +162,41 @@ struct PassPlan {
         for (int p = 0; p + 1 < NP; ++p) r = padded(p) > r ? padded(p) : r;
         return r | 1;   // odd stride between units
     }
+    // LDS of an exchange done in two rounds (half of the rows each)
+    static constexpr int half_region() {
+        int r = 0;
+        for (int p = 0; p + 1 < NP; ++p) r = padded(p) / 2 > r ? padded(p) / 2 : r;
+        return r;
+    }
 };
+
+// Exchanges in two rounds: a whole-transform unit (one per workgroup) whose
+// exchange would not fit in LDS writes and reads half of the exchange's rows
+// per round (binary16 2^16 points: 256 KiB of data, 128-135 KiB per round).
+// Each pass after an exchange must hold at least two groups per lane (the
+// rounds split a lane's groups in halves).
+constexpr size_t kLdsBytes = 160 * 1024;
+template <class E, int LOG_E, int MODE, int UPW, class PP>
+constexpr int exchange_rounds() {
+    if (!(MODE == MODE_SMALL && UPW == 1 && PP::NP > 1 && (size_t)PP::region() * sizeof(E) > kLdsBytes))
+        return 1;
+    for (int p = 1; p < PP::NP; ++p)
+        if (PP::lr(p) >= LOG_E) return 1;
+    return 2;
+}
+// LDS elements of a workgroup.
+template <class E, int LOG_E, int MODE, int UPW, class PP>
+constexpr size_t unit_lds_elems() {
+    return exchange_rounds<E, LOG_E, MODE, UPW, PP>() == 2 ? (size_t)PP::half_region()
+                                                           : (size_t)UPW * PP::region();
+}
+// Whether a configuration fits a workgroup's LDS for element type E (the
+// configuration list serves both element sizes; entries that do not fit are
+// neither compiled nor offered).
+template <class E, int LOG_E, int MODE, int UPW, class PP>
+constexpr bool unit_fits() {
+    return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) <= kLdsBytes;
+}
 
 // ------------------------------------------------------------------ the kernel
 
@@ -375,10 +409,11 @@ __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
 // Twiddles of register pass P for this lane's groups: tw[u * R + c] is the
 // entry of butterfly index c (1 <= c < R) of group g + G u.  Entries depend on
 // the lane's position only, not on data.
+// (group_twiddles: the same for one group, tw[c].)
 template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P>
-__device__ __forceinline__ void pass_twiddles(typename TwOf<E>::type* tw,
-                                              const typename TwOf<E>::type* __restrict__ lt,
-                                              const UnitGeom& geo0, int g) {
+__device__ __forceinline__ void group_twiddles(typename TwOf<E>::type* tw,
+                                               const typename TwOf<E>::type* __restrict__ lt,
+                                               const UnitGeom& geo0, int g, int u) {
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NU = 1 << LOG_NU;
     constexpr int EL = 1 << LOG_E;
@@ -386,20 +421,27 @@ __device__ __forceinline__ void pass_twiddles(typename TwOf<E>::type* tw,
     constexpr int R = 1 << PP::lr(P);
     constexpr int L0 = 1 << PP::log_l0(P);
     constexpr int LOGM = PP::log_m(P);
-    constexpr int GPL = EL / R;
+    const int q = (g + G * u) >> LOGM;        // column within the unit
+    if constexpr (P == 0 && MODE != MODE_ROWS) {
 #pragma unroll
-    for (int u = 0; u < GPL; ++u) {
-        const int q = (g + G * u) >> LOGM;    // column within the unit
-        if constexpr (P == 0 && MODE != MODE_ROWS) {
+        for (int c = 1; c < R; ++c) tw[c] = lt[c];
+    } else {
+        const int qg = geo0.q0 + (q << geo0.log_lb);
+        const int lg0 = L0 << geo0.log_lb;
 #pragma unroll
-            for (int c = 1; c < R; ++c) tw[u * R + c] = lt[c];
-        } else {
-            const int qg = geo0.q0 + (q << geo0.log_lb);
-            const int lg0 = L0 << geo0.log_lb;
-#pragma unroll
-            for (int c = 1; c < R; ++c) tw[u * R + c] = lt[qg + lg0 * c];
-        }
+        for (int c = 1; c < R; ++c) tw[c] = lt[qg + lg0 * c];
     }
+}
+template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P>
+__device__ __forceinline__ void pass_twiddles(typename TwOf<E>::type* tw,
+                                              const typename TwOf<E>::type* __restrict__ lt,
+                                              const UnitGeom& geo0, int g) {
+    using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+    constexpr int R = 1 << PP::lr(P);
+    constexpr int GPL = (1 << LOG_E) / R;
+#pragma unroll
+    for (int u = 0; u < GPL; ++u)
+        group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw + u * R, lt, geo0, g, u);
 }
 
 // Twiddle prefetch (configurations with PIPE = 2): whole-transform units load
@@ -453,6 +495,9 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
         static_assert(UPL == 1 || (MODE == MODE_SMALL && !LANE && UPW % UPL == 0),
                       "several units per lane: whole-transform units without the lane tail");
+        constexpr int XR = exchange_rounds<E, LOG_E, MODE, UPW, PP>();
+        static_assert(XR == 1 || (UPL == 1 && !LANE && !STG && PRE == 0),
+                      "two-round exchanges: one plain unit per workgroup");
         const int tid = gp.tid();
         const int ul0 = unit_fast ? (tid % UPW) : (tid / G) * UPL;
         const int g0 = unit_fast ? (tid / UPW) : (tid % G);
@@ -493,6 +538,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
             }
         } else if constexpr (P == 0) {
             if constexpr (!PRE) load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(v, in, gp);
+        } else if constexpr (XR == 2) {
+            // gathered by the previous pass's two-round exchange
         } else {
             constexpr int PADP = PP::pad(P - 1);
 #pragma unroll
@@ -512,17 +559,17 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
-        TW tw[GPL * R];
-        if constexpr (PF && P > 0) {
-#pragma unroll
-            for (int i = 0; i < GPL * R; ++i) tw[i] = twp[i];
-        } else {
-            pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g);
-        }
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
+            TW tw[R];
+            if constexpr (PF && P > 0) {
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw + u * R);
+                for (int c = 1; c < R; ++c) tw[c] = twp[u * R + c];
+            } else {
+                group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
+            }
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw);
         }
         if constexpr (PF && P + 1 < NP) {
             // entries c >= 1 of each group are the loaded ones
@@ -559,6 +606,48 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                     __builtin_nontemporal_store(v[2 * k + 1], out + geo0.base_out + jb + NU / 2);
                 }
             }
+        } else if constexpr (P + 1 < NP && XR == 2) {
+            // Two rounds over the exchange's NR = L0 R rows: round h moves rows
+            // [h NR/2, (h+1) NR/2).  The rows a lane writes in round h are its
+            // elements e in [h R/2, (h+1) R/2) (row q + L0 e, q < L0); the rows
+            // the next pass reads in round h are those of its groups
+            // u1 in [h GPL1/2, (h+1) GPL1/2) (row q1 = (g + G u1) / M1 <
+            // NR/2 exactly when u1 < GPL1/2).  So each lane moves half of its
+            // registers per round, and the next pass's values go to a second
+            // array until every value of this pass has been written.
+            constexpr int PAD = PP::pad(P);
+            constexpr int NR = L0 * R;
+            constexpr int R1 = 1 << PP::lr(P + 1);
+            constexpr int LOGM1 = PP::log_m(P + 1);
+            constexpr int M1 = 1 << LOGM1;
+            constexpr int GPL1 = EL / R1;
+            static_assert(GPL1 >= 2 && R >= 2 && UPW == 1, "two-round exchange: halves of groups and rows");
+            E w[EL];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (h > 0 || P > 0) __syncthreads();   // readers of LDS are done
+#pragma unroll
+                for (int u = 0; u < GPL; ++u) {
+                    const int gam = g + G * u;
+                    const int r = gam & (M - 1);
+                    const int q = gam >> LOGM;
+#pragma unroll
+                    for (int e = h * (R / 2); e < (h + 1) * (R / 2); ++e)
+                        lds[r + (M + PAD) * (q + L0 * e - h * (NR / 2))] = v[u * R + e];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int u1 = h * (GPL1 / 2); u1 < (h + 1) * (GPL1 / 2); ++u1) {
+                    const int gam1 = g + G * u1;
+                    const int r1 = gam1 & (M1 - 1);
+                    const int q1 = gam1 >> LOGM1;
+                    const int basep = r1 + (M + PAD) * (q1 - h * (NR / 2));
+#pragma unroll
+                    for (int i = 0; i < R1; ++i) w[u1 * R1 + i] = lds[basep + M1 * i];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < EL; ++i) v[i] = w[i];
         } else if constexpr (P + 1 < NP) {
             constexpr int PAD = PP::pad(P);
             if constexpr (P > 0 || STG) __syncthreads();   // readers of LDS are done

@@ -17,23 +17,34 @@ const void* batch_kernel_func(int dtype) {
     return dtype == 0 ? (const void*)&fft_batch_kernel<uint32_t> : (const void*)&fft_batch_kernel<f2_t>;
 }
 
-// The binary16 2^15-point list kernel: 1024 threads (32 elements each),
-// radix 2^5 passes, one transform per workgroup.
-#define DSFFT_BIG_KERNEL fft_list_kernel<uint32_t, kBigListLog, 5, 5, 5, 5>
+// The binary16 list kernels, 1024 threads each: 2^16 points with 64 elements
+// per lane (radix 2^6, 2^5, 2^5; each exchange in two rounds of half the rows)
+// and 2^15 points with 32 (radix 2^5 passes).
+#define DSFFT_LIST16 fft_list_kernel<uint32_t, 16, 6, 6, 5, 5>
+#define DSFFT_LIST15 fft_list_kernel<uint32_t, 15, 5, 5, 5, 5>
+static_assert(kListLog[0] == 16 && kListLog[1] == 15 && kListThreads == (1 << (16 - 6)) &&
+                  kListThreads == (1 << (15 - 5)),
+              "list kernel geometry");
 
-size_t batch_big_lds_bytes() {
-    return (size_t)PassPlan<kBigListLog, 5, 5, 5, 0>::region() * sizeof(uint32_t);
+size_t batch_list_lds_bytes(int list) {
+    return list == 0 ? unit_lds_elems<uint32_t, 6, MODE_SMALL, 1, PassPlan<16, 6, 5, 5, 0>>() * sizeof(uint32_t)
+                     : unit_lds_elems<uint32_t, 5, MODE_SMALL, 1, PassPlan<15, 5, 5, 5, 0>>() * sizeof(uint32_t);
 }
 
-const void* batch_big_func() { return (const void*)&DSFFT_BIG_KERNEL; }
+const void* batch_list_func(int list) {
+    return list == 0 ? (const void*)&DSFFT_LIST16 : (const void*)&DSFFT_LIST15;
+}
 
-hipError_t launch_batch_big(const void* in, void* out, const void* lt, const int64_t* offs,
-                            int64_t count, hipStream_t s) {
-    static_assert(kBigListThreads == (1 << (kBigListLog - 5)), "list kernel geometry");
+hipError_t launch_batch_list(int list, const void* in, void* out, const void* lt, const int64_t* offs,
+                             int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(DSFFT_BIG_KERNEL, dim3((unsigned)count), dim3(kBigListThreads),
-                       batch_big_lds_bytes(), s, (const uint32_t*)in, (uint32_t*)out, (const TwH*)lt,
-                       offs, count);
+    if (count > 0x7fffffffLL || list < 0 || list >= kNumLists) return hipErrorInvalidValue;
+    if (list == 0)
+        hipLaunchKernelGGL(DSFFT_LIST16, dim3((unsigned)count), dim3(kListThreads), batch_list_lds_bytes(0), s,
+                           (const uint32_t*)in, (uint32_t*)out, (const TwH*)lt, offs, count);
+    else
+        hipLaunchKernelGGL(DSFFT_LIST15, dim3((unsigned)count), dim3(kListThreads), batch_list_lds_bytes(1), s,
+                           (const uint32_t*)in, (uint32_t*)out, (const TwH*)lt, offs, count);
     return hipGetLastError();
 }
 

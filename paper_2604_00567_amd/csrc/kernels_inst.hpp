@@ -6,15 +6,32 @@
 
 namespace dsfft {
 
-// The kernel entry for a configuration: the pipelined entry (with its
-// occupancy attribute) only where PIPE = 1.
+// Whether the configuration fits a workgroup's LDS with element type E.
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int LANE>
+static constexpr bool cfg_fits() {
+    return unit_fits<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
+}
+
+// The kernel of a configuration: the pipelined entry (with its occupancy
+// attribute) only where PIPE = 1.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE>
-static constexpr auto kernel_entry() {
+static constexpr auto kernel_ptr() {
     if constexpr (PIPE == 1)
         return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
     else
         return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
+}
+
+// Its entry for the registry; none for a configuration that does not fit
+// (that kernel is not instantiated).
+template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
+static constexpr const void* kernel_entry() {
+    if constexpr (!cfg_fits<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>())
+        return nullptr;
+    else
+        return (const void*)kernel_ptr<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
 }
 
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
@@ -22,10 +39,13 @@ template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, i
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
     using TW = typename TwOf<E>::type;
+    if constexpr (!cfg_fits<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>()) {
+        return hipErrorInvalidConfiguration;
+    } else {
     constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
     constexpr size_t LDS =
-        (size_t)UPW * PassPlan<LOG_NU, LR0, LR1, LR2, LANE>::region() * sizeof(E);
-    auto kern = kernel_entry<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+        unit_lds_elems<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() * sizeof(E);
+    auto kern = kernel_ptr<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
     int64_t grid = (units + UPW - 1) / UPW;
     if (grid <= 0) return hipSuccess;
     if (PIPE == 1) {
@@ -45,15 +65,19 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), LDS, stream, (const E*)in, (E*)out,
                        (const TW*)lt, units, log_m);
     return hipGetLastError();
+    }
 }
 
+// An entry that does not fit gets mode -1: no plan or tuner ever selects it.
 #define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \
-    {DTYPE_ID, MODE, LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE,                \
+    {DTYPE_ID,                                                                                 \
+     cfg_fits<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>() ? (MODE) : -1,          \
+     LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE,                                 \
      ((UPW) / (UPL)) << ((LOG_NU) - (LOG_E)),                                                  \
-     (size_t)(UPW) * PassPlan<LOG_NU, LR0, LR1, LR2, LANE>::region() * sizeof(ELEM_T),         \
+     unit_lds_elems<ELEM_T, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() *        \
+         sizeof(ELEM_T),                                                                       \
      &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>,      \
-     (const void*)kernel_entry<ELEM_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE,   \
-                               PIPE>()},
+     kernel_entry<ELEM_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()},
 #define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE)                          \
     CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, 1)
 

@@ -30,7 +30,8 @@ struct fft_serve_slot {
     int cfg_choice[17] = {};
     hipEvent_t done = nullptr;
     bool launched = false;
-    std::vector<int64_t> tn, toff, offs, big;
+    std::vector<int64_t> tn, toff, offs, lists;
+    int64_t nlist[dsfft::kNumLists] = {};
     std::vector<dsfft::HostBatchItem> items;
     ~fft_serve_slot();
 };
@@ -116,30 +117,33 @@ int fft_serve_slot_launch(fft_serve_slot* s, const int64_t* n, const int64_t* ba
             s->tn.push_back(v);
             s->toff.push_back(off[r] + j * v);
         }
-        if (v >= (int64_t(1) << 15)) nlarge += batch[r];
+        if (v > (int64_t(1) << max_whole_log(s->dtype))) nlarge += batch[r];
     }
     int64_t ws_elems = 0, phase0 = 0;
     build_work(s->tn.data(), s->toff.data(), (int64_t)s->tn.size(), s->cfg_choice,
-               big_log_for(s->dtype), s->items, s->offs, s->big, ws_elems, phase0);
+               lists_for(s->dtype), s->items, s->offs, s->lists, s->nlist, ws_elems, phase0);
     if ((int64_t)s->items.size() > s->item_cap ||
-        (int64_t)(s->offs.size() + s->big.size()) > s->offs_cap || nlarge > s->slot_cap ||
+        (int64_t)(s->offs.size() + s->lists.size()) > s->offs_cap || nlarge > s->slot_cap ||
         (size_t)ws_elems * elem_bytes(s->dtype) > s->ws_cap)
         return set_error(FFT_ENOMEM, "step exceeds the slot's capacity");
-    if (s->items.empty() && s->big.empty()) return FFT_OK;
+    if (s->items.empty() && s->lists.empty()) return FFT_OK;
     // staging layout: work items, single-unit offsets, list-kernel offsets
     const size_t ib = sizeof(HostBatchItem) * s->items.size();   // a multiple of 8
     const size_t ob = sizeof(int64_t) * s->offs.size();
-    const size_t bb = sizeof(int64_t) * s->big.size();
+    const size_t bb = sizeof(int64_t) * s->lists.size();
     std::memcpy(s->h_stage, s->items.data(), ib);
     std::memcpy(s->h_stage + ib, s->offs.data(), ob);
-    std::memcpy(s->h_stage + ib + ob, s->big.data(), bb);
+    std::memcpy(s->h_stage + ib + ob, s->lists.data(), bb);
     if ((e = hipMemcpyAsync(s->d_stage, s->h_stage, ib + ob + bb, hipMemcpyHostToDevice, st)) !=
         hipSuccess)
         return hip_error(e, "hipMemcpyAsync(work list)");
-    if (!s->big.empty() &&
-        (e = launch_batch_big(data, data, s->table->ptr, (const int64_t*)(s->d_stage + ib + ob),
-                              (int64_t)s->big.size(), st)) != hipSuccess)
-        return hip_error(e, "launch(list)");
+    const int64_t* d_lists = (const int64_t*)(s->d_stage + ib + ob);
+    for (int i = 0; i < kNumLists; ++i) {
+        if (s->nlist[i] && (e = launch_batch_list(i, data, data, s->table->ptr, d_lists, s->nlist[i], st)) !=
+                               hipSuccess)
+            return hip_error(e, "launch(list)");
+        d_lists += s->nlist[i];
+    }
     const int64_t n1 = (int64_t)s->items.size() - phase0;
     const int grid0 = (int)std::max<int64_t>(1, std::min<int64_t>(phase0, s->resident));
     const int grid1 = (int)std::max<int64_t>(1, std::min<int64_t>(n1, s->resident));

@@ -28,7 +28,14 @@ from . import binding
 
 ELEM_BYTES = {"f16": 4, "f32": 8}
 TORCH_DTYPE = {"f16": torch.float16, "f32": torch.float32}
-LARGE = 1 << 15          # transforms this size and up use the column/row split
+# log2 of the largest transform that runs whole (binary16: the 2^15 and 2^16
+# list kernels; binary32: whole-transform work items); larger ones take the
+# column/row split and a workspace slice
+MAX_WHOLE_LOG = {"f16": 16, "f32": 14}
+
+
+def is_split(n: int, dtype: str) -> bool:
+    return n > (1 << MAX_WHOLE_LOG[dtype])
 
 
 def latency_summary(latency_s: np.ndarray) -> dict:
@@ -58,12 +65,12 @@ def admit_step(pending, head, trace, inflight, budget, fits, max_step_requests, 
     while head < len(pending) and len(take) < max_step_requests:
         rid = pending[head]
         n, b, dt = int(trace["n"][rid]), int(trace["batch"][rid]), str(trace["dtype"][rid])
-        ws = n * b * ELEM_BYTES[dt] if n >= LARGE else 0
+        ws = n * b * ELEM_BYTES[dt] if is_split(n, dt) else 0
         if inflight + nbytes[rid] + ws > budget or not fits(plan, n, b, dt):
             break
         p = plan[dt]
         p[0] += n * b
-        if n >= LARGE:
+        if is_split(n, dt):
             p[2] += b
             p[3] += n * b
         else:
@@ -130,7 +137,7 @@ class Server:
         cap = self.slot_bytes // ELEM_BYTES[dt]
         if used + elems > cap:
             return False
-        if n >= LARGE:
+        if is_split(n, dt):
             if large + b > self.max_large or (ws + elems) * ELEM_BYTES[dt] > self.slot_bytes:
                 return False
         elif transforms + b > self.max_transforms:
@@ -150,7 +157,7 @@ class Server:
             per_dt[dt].append((rid, n, b, off))
             slot.placement[rid] = (dt, off, n, b)
             p[0] += n * b
-            if n >= LARGE:
+            if is_split(n, dt):
                 p[2] += b
                 p[3] += n * b
             else:

@@ -26,8 +26,15 @@ def check(sizes, dtype="f16"):
     items, phase0, offs, lst, ws = binding.fft_batch_work_list(sizes, dtype)
     assert np.all(items[:phase0, F["phase"]] == 0) and np.all(items[phase0:, F["phase"]] == 1)
     starts = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    # binary16 2^15 transforms run whole in the list kernel; larger ones split
-    listed = (sizes == (1 << 15)) if dtype == "f16" else np.zeros(sizes.shape, bool)
+    # binary16 2^16 and 2^15 transforms run whole in the list kernels (the
+    # 2^16 list first); larger ones split
+    if dtype == "f16":
+        listed = (sizes == (1 << 15)) | (sizes == (1 << 16))
+        n16 = int(np.sum(sizes == (1 << 16)))
+        assert sorted(int(v) for v in lst[:n16]) == sorted(int(v) for v in starts[sizes == (1 << 16)])
+        assert sorted(int(v) for v in lst[n16:]) == sorted(int(v) for v in starts[sizes == (1 << 15)])
+    else:
+        listed = np.zeros(sizes.shape, bool)
     assert sorted(int(v) for v in lst) == sorted(int(v) for v in starts[listed])
     large = (sizes >= (1 << 15)) & ~listed
     assert ws == int(sizes[large].sum())
@@ -100,7 +107,7 @@ def test_work_list_mixed_sizes(dtype):
 
 
 def test_work_list_order():
-    sizes = inputs.uneven_sizes(600, seed=7, log_lo=6, log_hi=17)
+    sizes = inputs.uneven_sizes(600, seed=7, log_lo=6, log_hi=18)
     items, _, _ = check(sizes)
     kinds = [classify(it) for it in items]
     # columns, then whole transforms (largest first), then rows
@@ -113,11 +120,16 @@ def test_work_list_order():
 def test_work_list_only_small_or_only_large():
     items, phase0, offs, lst, ws = binding.fft_batch_work_list([64] * 100)
     assert phase0 == len(items) and ws == 0 and len(offs) == 100 and len(lst) == 0
-    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 16] * 3)
-    assert 0 < phase0 < len(items) and ws == 3 << 16 and len(offs) == 0
-    check([1 << 16] * 3)
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 17] * 3)
+    assert 0 < phase0 < len(items) and ws == 3 << 17 and len(offs) == 0
+    check([1 << 17] * 3)
     items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 15] * 5, "f16")
     assert len(items) == 0 and ws == 0 and list(lst) == [i << 15 for i in range(5)]
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 15, 1 << 16, 1 << 15], "f16")
+    assert len(items) == 0 and ws == 0 and list(lst) == [1 << 15, 0, 3 << 15]
+    items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 16] * 3, "f32")
+    assert 0 < phase0 < len(items) and ws == 3 << 16 and len(lst) == 0
+    check([1 << 16] * 3, "f32")
     items, phase0, offs, lst, ws = binding.fft_batch_work_list([1 << 15] * 5, "f32")
     assert len(items) > 0 and ws == 5 << 15 and len(lst) == 0
 

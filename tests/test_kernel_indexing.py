@@ -64,6 +64,29 @@ class PassPlan:
             r = max(r, self.padded(p))
         return r | 1
 
+    def half_region(self):
+        return max(self.padded(p) // 2 for p in range(self.np - 1))
+
+
+LDS_BYTES = 160 * 1024
+
+
+def exchange_rounds(pp, mode, upw, log_e, esize):
+    """Two rounds (half of the exchange's rows each) for a lone whole-transform
+    unit whose exchange does not fit, when each later pass has two or more
+    groups per lane."""
+    if not (mode == 0 and upw == 1 and pp.np > 1 and pp.region() * esize > LDS_BYTES):
+        return 1
+    if any(pp.lr(p) >= log_e for p in range(1, pp.np)):
+        return 1
+    return 2
+
+
+def lds_elems(pp, mode, upw, log_e, esize):
+    if exchange_rounds(pp, mode, upw, log_e, esize) == 2:
+        return pp.half_region()
+    return upw * pp.region()
+
 
 def level_twiddle(idx):
     """Entry idx of the level-ordered table: L/2 + j -> W_L^j."""
@@ -114,13 +137,16 @@ def lane_tail_model(v, NU, EL, NT, tcap):
                 v[w0:w0 + 64, 2 * k], v[w0:w0 + 64, 2 * k + 1] = x, y
 
 
-def simulate(cfg, n, batch, x=None):
+def simulate(cfg, n, batch, x=None, esize=4):
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane = cfg
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     NU, EL = 1 << log_nu, 1 << log_e
     G = NU // EL
     NT = upw * G
     RS = pp.region()
+    XR = exchange_rounds(pp, mode, upw, log_e, esize)
+    LDS = lds_elems(pp, mode, upw, log_e, esize)
+    assert LDS * esize <= LDS_BYTES, "configuration does not fit"
     log_m = (n.bit_length() - 1) - log_nu
     units = batch if mode == 0 else batch << log_m
     if x is None:
@@ -131,8 +157,9 @@ def simulate(cfg, n, batch, x=None):
     tcap = max(n, 4096)
     grid = (units + upw - 1) // upw
     for blk in range(grid):
-        lds = np.full(upw * RS, np.nan + 0j)
-        lds_gen = np.full(upw * RS, -1)
+        lds = np.full(max(LDS, upw * RS), np.nan + 0j)
+        lds_gen = np.full(max(LDS, upw * RS), -1)
+        pre = None                                 # next pass's values (two-round exchange)
         v = np.zeros((NT, EL), complex)
         for p in range(pp.np):
             LR = pp.lr(p)
@@ -191,6 +218,8 @@ def simulate(cfg, n, batch, x=None):
                                 a = base_in + idx * in_s
                                 assert 0 <= a < batch * n
                                 vv[u * R + i] = x[a]
+                    elif XR == 2:
+                        vv[u * R:(u + 1) * R] = pre[tid][u * R:(u + 1) * R]
                     else:
                         padp = pp.pad(p - 1)
                         r, q = gam & (M - 1), gam >> LOGM
@@ -231,6 +260,42 @@ def simulate(cfg, n, batch, x=None):
             if lane and p == pp.np - 1:
                 assert G == 64 and GPL == 1 and M == 4 and L0 == 16 and mode == 0
                 lane_tail_model(newv, NU, EL, NT, tcap)
+            if XR == 2 and p + 1 < pp.np:
+                # two rounds of half the rows: writes of elements e in half h,
+                # then reads of the next pass's groups u1 in half h
+                pad = pp.pad(p)
+                NR = L0 * R
+                R1, LOGM1 = 1 << pp.lr(p + 1), pp.log_m(p + 1)
+                M1, GPL1 = 1 << LOGM1, EL // (1 << pp.lr(p + 1))
+                assert GPL1 >= 2 and upw == 1 and not lane and not stg
+                pre = np.full((NT, EL), np.nan + 0j)
+                for h in range(2):
+                    gen = 100 + 2 * p + h
+                    for tid in range(NT):
+                        g = tid % G
+                        for u in range(GPL):
+                            gam = g + G * u
+                            r, q = gam & (M - 1), gam >> LOGM
+                            for e in range(h * (R // 2), (h + 1) * (R // 2)):
+                                a = r + (M + pad) * (q + L0 * e - h * (NR // 2))
+                                assert 0 <= a < LDS, "round write outside the half region"
+                                assert lds_gen[a] != gen, "two writes to one LDS slot in a round"
+                                lds[a] = newv[tid][u * R + e]
+                                lds_gen[a] = gen
+                    for tid in range(NT):
+                        g = tid % G
+                        for u1 in range(h * (GPL1 // 2), (h + 1) * (GPL1 // 2)):
+                            gam1 = g + G * u1
+                            r1, q1 = gam1 & (M1 - 1), gam1 >> LOGM1
+                            basep = r1 + (M + pad) * (q1 - h * (NR // 2))
+                            for i in range(R1):
+                                a = basep + M1 * i
+                                assert 0 <= a < LDS
+                                assert lds_gen[a] == gen, "round read of a slot not written in it"
+                                pre[tid][u1 * R1 + i] = lds[a]
+                assert not np.any(np.isnan(pre))
+                v = newv
+                continue
             # every lane has gathered before any lane scatters (the kernel's barrier)
             for tid in range(NT):
                 ul, g, active, reg, base_out, out_s = geos[tid]

@@ -3,7 +3,8 @@ synthetic clock, in-order admission under the HBM budget, the trace recipe."""
 import numpy as np
 
 from paper_2604_00567_amd import inputs
-from paper_2604_00567_amd.serve import ELEM_BYTES, LARGE, admit_step, latency_summary, request_bytes
+from paper_2604_00567_amd import binding
+from paper_2604_00567_amd.serve import ELEM_BYTES, admit_step, is_split, latency_summary, request_bytes
 
 
 def test_latency_summary_synthetic_clock():
@@ -37,9 +38,15 @@ def test_admission_respects_budget_and_order():
             inflight = 0
             continue
         assert take == pending[head:head2]       # arrival order, no skipping
-        ws = sum(int(tr["n"][r]) * int(tr["batch"][r]) * ELEM_BYTES[str(tr["dtype"][r])]
-                 for r in take if tr["n"][r] >= LARGE)
-        assert inflight2 <= budget and inflight2 + ws <= budget + ws
+        # in flight grows by the requests' bytes; each was admitted only with
+        # room for its workspace too (the slot's own arena holds it)
+        assert inflight2 == inflight + sum(nb[r] for r in take)
+        room = inflight
+        for r in take:
+            n, dt = int(tr["n"][r]), str(tr["dtype"][r])
+            ws = n * int(tr["batch"][r]) * ELEM_BYTES[dt] if is_split(n, dt) else 0
+            assert room + nb[r] + ws <= budget
+            room += nb[r]
         seen += take
         head, inflight = head2, inflight2
         steps += 1
@@ -57,3 +64,14 @@ def test_trace_recipe():
     assert logn.min() >= 8 and logn.max() <= 18
     assert tr["batch"].min() >= 1 and tr["batch"].max() <= 64
     assert 0.72 < np.mean(tr["dtype"] == "f16") < 0.78
+
+
+def test_split_rule_matches_the_library():
+    """The serving loop reserves workspace exactly for the transforms the
+    library splits into column and row items (its work list's workspace)."""
+    for dt in ("f16", "f32"):
+        for m in range(1, 19):
+            n = 1 << m
+            _, _, _, _, ws = binding.fft_batch_work_list([n, n], dt)
+            assert (ws > 0) == is_split(n, dt), (dt, m)
+            assert ws == (2 * n if is_split(n, dt) else 0)
