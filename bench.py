@@ -237,7 +237,7 @@ def bench_uneven(torch, binding, inputs, steps, warmup):
             "pct_hbm_peak": 100 * algo / wall / 1e9 / HBM_PEAK_GBS,
             "items": info["items"], "grid": info["grid"],
             "per_class_plans_gbs": algo / wall_c / 1e9, "per_class_launches": len(plans),
-            "form": "one HIP-graph replay per step (reset, two persistent kernels)"}
+            "form": "one HIP-graph replay per step: the 2^16 and 2^15 list kernels and the persistent kernel's phase 0 as parallel branches, then phase 1"}
 
 
 def bench_sweep(torch, binding, inputs, steps):

@@ -184,7 +184,8 @@ int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* ro
  * orders each transform's row items after its column items.  Binary16
  * transforms of 2^16 and 2^15 points (256 and 128 KiB, more than the batch
  * kernel's LDS) run whole in two list kernels of their own, one transform per
- * 1024-thread workgroup, over lists of their offsets, before the two.  The
+ * 1024-thread workgroup, over lists of their offsets, concurrently with the
+ * first (graph branches with no dependency: the transforms are disjoint).  The
  * launches form one HIP graph built at the first execute and replayed by
  * every execute (the kernels leave their work-queue counters at zero for the
  * next replay); new data pointers are set on the graph's kernel nodes.  The

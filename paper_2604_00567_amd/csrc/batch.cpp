@@ -301,21 +301,22 @@ static hipKernelNodeParams list_params(const fft_batch* b, ListArgs& a, int list
     return kp;
 }
 
-// Builds the graph once: the list kernels (those with transforms), then
-// phase 0, then phase 1 (each a persistent kernel).
+// Builds the graph once: the list kernels (those with transforms) and phase 0
+// as independent roots (they touch disjoint transforms, so each can fill the
+// others' tails), then phase 1 after phase 0 (each phase a persistent kernel
+// whose workgroups only claim items from a queue, so sharing the device with
+// the list kernels never blocks them).
 static int build_graph(fft_batch* b, const void* in, void* out) {
     hipError_t e;
     if ((e = hipGraphCreate(&b->graph, 0)) != hipSuccess) return hip_error(e, "hipGraphCreate");
-    hipGraphNode_t prev = nullptr;
     for (int i = 0; i < kNumLists; ++i) {
         if (b->nlist[i] == 0) continue;
         ListArgs la(b, in, out, i);
         hipKernelNodeParams kp = list_params(b, la, i);
-        if ((e = hipGraphAddKernelNode(&b->lnode[i], b->graph, prev ? &prev : nullptr, prev ? 1 : 0,
-                                       &kp)) != hipSuccess)
+        if ((e = hipGraphAddKernelNode(&b->lnode[i], b->graph, nullptr, 0, &kp)) != hipSuccess)
             return hip_error(e, "hipGraphAddKernelNode(list)");
-        prev = b->lnode[i];
     }
+    hipGraphNode_t prev = nullptr;
     for (int ph = 0; ph < 2; ++ph) {
         PhaseArgs a(b, in, out, ph);
         if (a.nitems == 0) continue;

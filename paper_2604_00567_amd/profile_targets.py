@@ -1,7 +1,7 @@
 """Short, fixed workloads to run under a profiler (rocprofv3 --kernel-trace,
 --pmc): each executes a plan or batch a few times on synthetic data and exits.
 
-    python -m paper_2604_00567_amd.profile_targets two_pass   # N = 2^15..2^20
+    python -m paper_2604_00567_amd.profile_targets large      # N = 2^15..2^20
     python -m paper_2604_00567_amd.profile_targets batch      # uneven batch
     python -m paper_2604_00567_amd.profile_targets fixed N BATCH DTYPE
 """
@@ -27,9 +27,11 @@ def run_fixed(n: int, batch: int, dtype: str, reps: int = 6) -> None:
     p.close()
 
 
-def two_pass() -> None:
-    """binary16 N = 2^15, 2^16, 2^18, 2^20 and binary32 N = 2^16, batch 2^26 / N."""
-    for m, dt in ((15, "f16"), (16, "f16"), (18, "f16"), (20, "f16"), (16, "f32")):
+def large() -> None:
+    """batch 2^26 / N: binary16 N = 2^15, 2^16 (one kernel each), 2^17, 2^18,
+    2^20 (two-pass) and binary32 N = 2^15, 2^16 (two-pass)."""
+    for m, dt in ((15, "f16"), (16, "f16"), (17, "f16"), (18, "f16"), (20, "f16"), (15, "f32"),
+                  (16, "f32")):
         run_fixed(1 << m, (1 << 26) >> m, dt)
         torch.cuda.empty_cache()
 
@@ -49,8 +51,8 @@ def batch() -> None:
 
 def main(argv) -> int:
     torch.cuda.set_stream(torch.cuda.Stream())
-    if argv[:1] == ["two_pass"]:
-        two_pass()
+    if argv[:1] == ["large"]:
+        large()
     elif argv[:1] == ["batch"]:
         batch()
     elif argv[:1] == ["fixed"] and len(argv) == 4:

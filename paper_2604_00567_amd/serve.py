@@ -97,15 +97,25 @@ class _Slot:
 
 class Server:
     """K-slot continuous-batching server.  ``budget_bytes`` caps the request
-    data (plus large-transform workspace) admitted but not yet completed."""
+    data (plus large-transform workspace) admitted but not yet completed.
+
+    A step of at most ``direct_max`` requests that all run whole (no
+    column/row split) launches each request through a cached plan on the
+    slot's stream, in place in the slot's arena: for one or two requests that
+    is one kernel each, where the batch kernels add a staging copy and a list
+    or phase launch.  Larger steps run the batch kernels.  Both forms compute
+    every transform with the same butterflies and table, bit for bit."""
 
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, slot_bytes: int = 1 << 30,
                  kind: str = "dual_select", max_transforms: int = 1 << 15,
                  max_large: int = 1 << 12, max_items: int = 1 << 18, seed: int = 0,
-                 keep_io: bool = False):
+                 keep_io: bool = False, direct_max: int = 2):
         self.budget = int(budget_bytes)
         self.kind = kind
         self.keep_io = keep_io
+        self.direct_max = int(direct_max)
+        self.plans = {}
+        self.direct_steps = 0
         self.gen = torch.Generator(device="cuda")
         self.gen.manual_seed(seed)
         self.slots = []
@@ -129,6 +139,15 @@ class Server:
             for h in s.native.values():
                 binding.fft_serve_slot_destroy(h)
         self.slots = []
+        for p in self.plans.values():
+            p.close()
+        self.plans = {}
+
+    def _plan(self, n, b, dt):
+        key = (n, b, dt)
+        if key not in self.plans:
+            self.plans[key] = binding.Plan(n, b, dt, self.kind)
+        return self.plans[key]
 
     # ------------------------------------------------------------------ steps
     def _fits(self, plan, n, b, dt):
@@ -162,6 +181,9 @@ class Server:
                 p[3] += n * b
             else:
                 p[1] += b
+        direct = len(reqs) <= self.direct_max and not any(
+            is_split(n, dt) for dt, lst in per_dt.items() for _, n, _, _ in lst)
+        self.direct_steps += int(direct)
         with torch.cuda.stream(slot.stream):
             for dt, lst in per_dt.items():
                 if not lst:
@@ -172,6 +194,11 @@ class Server:
                 if self.keep_io:
                     for rid, n, b, off in lst:
                         self.inputs[rid] = region[off * 2:(off + n * b) * 2].clone()
+                if direct:
+                    for _, n, b, off in lst:
+                        view = slot.arena[dt][off * 2:(off + n * b) * 2].view(b, n, 2)
+                        self._plan(n, b, dt).execute(view, view, stream=slot.stream)
+                    continue
                 arr = np.asarray([(n, b, off) for _, n, b, off in lst], dtype=np.int64)
                 binding.fft_serve_slot_launch(slot.native[dt], arr[:, 0], arr[:, 1], arr[:, 2],
                                               slot.arena[dt].data_ptr(), slot.stream.cuda_stream)
@@ -250,7 +277,8 @@ class Server:
                     "mean_requests_per_step": float(np.mean(reqs_per_step)) if reqs_per_step else 0,
                     "gbs": float(np.sum(nb) / wall / 1e9), "wall_s": float(wall),
                     "max_inflight_bytes": int(max_inflight), "budget_bytes": self.budget,
-                    "max_concurrent_steps": int(max_busy), "slots": len(self.slots)})
+                    "max_concurrent_steps": int(max_busy), "slots": len(self.slots),
+                    "direct_steps": int(self.direct_steps), "direct_max": self.direct_max})
         return out
 
 

@@ -50,6 +50,45 @@ def test_results_alone_equal_results_in_mix():
         assert mismatches(y, oracle.emulate(x, "dual_select", dt)) == 0
 
 
+def test_small_steps_run_through_plans_with_the_same_results():
+    """At a low arrival rate most steps hold one or two requests and take the
+    direct form (one plan launch per request); their results equal the
+    batch-kernel form's and the oracle's."""
+    import torch
+    tr = small_trace(120, 24, rate=4000.0, log_hi=16)
+    outs = {}
+    for direct_max in (2, 0):
+        srv = Server(slots=2, slot_bytes=64 << 20, keep_io=True, seed=7, direct_max=direct_max)
+        try:
+            stats = srv.run(tr)
+            torch.cuda.synchronize()
+        finally:
+            srv.close()
+        assert stats["requests"] == tr["t"].size
+        if direct_max:
+            assert stats["direct_steps"] > 0
+        else:
+            assert stats["direct_steps"] == 0
+        outs[direct_max] = (dict(srv.inputs), dict(srv.outputs))
+    # the generator is seeded and advances per step, so inputs can differ
+    # between the runs: compare each run's outputs with a plan on its inputs
+    for direct_max, (ins, res) in outs.items():
+        for rid in range(0, tr["t"].size, 7):
+            n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+            x = ins[rid].reshape(b, n, 2)
+            y_alone = torch.empty_like(x)
+            p = binding.Plan(n, b, dt, "dual_select")
+            p.execute(x, y_alone)
+            torch.cuda.synchronize()
+            p.close()
+            assert mismatches(res[rid].reshape(b, n, 2).cpu().numpy(), y_alone.cpu().numpy()) == 0
+    ins, res = outs[2]
+    for rid in range(0, tr["t"].size, 30):
+        n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+        x = ins[rid].reshape(b, n, 2).cpu().numpy()
+        assert mismatches(res[rid].reshape(b, n, 2).cpu().numpy(), oracle.emulate(x, "dual_select", dt)) == 0
+
+
 def test_budget_is_respected():
     tr = small_trace(300, 22)
     budget = 48 << 20
