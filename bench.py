@@ -418,6 +418,16 @@ def main():
         inv.close()
         result["inverse_n1024"] = {"kernel_ms": round(dev * 1e3, 4),
                                    "gbs": round(2.0 * 1024 * 65536 * 4 / dev / 1e9, 1)}
+        log("binary16 storage, binary32 butterflies")
+        mix = binding.Plan(1024, 65536, "f16f32", "dual_select")
+        _, dev = timed_loop(torch, lambda i: mix.execute(xs_[i], ys_[i]), len(xs_), args.steps,
+                            args.warmup)
+        result["mixed_f16_f32_n1024"] = {
+            "kernel_ms": round(dev * 1e3, 4), "gbs": round(2.0 * 1024 * 65536 * 4 / dev / 1e9, 1),
+            "kernel": mix.info()["config"],
+            "error_vs_fp64": {k: error_vs_fp64(x0[pick], run_once(torch, binding, x0[pick], "f16f32", k))
+                              for k in ("dual_select", "linzer_feig")}}
+        mix.close()
         result["round_trip"] = bench_round_trip(torch, binding, inputs)
         del yout
         log("timing N=4096 x 16384 f16 dual-select")

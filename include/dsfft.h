@@ -15,7 +15,8 @@
  *
  * Data layout: interleaved complex, transform-contiguous.  Element n of
  * transform b sits at index b*N + n; an element is (re, im) as two binary16
- * values (FFT_F16, 4 bytes) or two binary32 values (FFT_F32, 8 bytes).
+ * values (FFT_F16 and FFT_F16_F32, 4 bytes) or two binary32 values (FFT_F32,
+ * 8 bytes).
  * Input and output use the same layout, output in natural frequency order.
  *
  * Pointers named in/out are device pointers (HBM), owned by the caller and
@@ -39,8 +40,17 @@ extern "C" {
 
 enum { FFT_OK = 0, FFT_EINVAL = -1, FFT_ENOMEM = -2, FFT_EHIP = -3, FFT_EUNSUPPORTED = -4 };
 
-/* Storage and arithmetic precision of data and table. */
-typedef enum { FFT_F16 = 0, FFT_F32 = 1 } fft_dtype;
+/*
+ * Storage and arithmetic precision of data and table.  FFT_F16_F32 (plans
+ * only; the precision variant the paper's discussion of mixed precision
+ * suggests, Sec. VI): binary16 storage in HBM, binary32 butterflies with the
+ * binary32 table.  Each input element is widened exactly, every pass computes
+ * in binary32 (LDS exchanges and the two-pass intermediate included), and each
+ * output element is rounded once, to nearest even, to binary16: the result is
+ * the FFT_F32 transform of the widened input, rounded once.  Uneven batches and
+ * serving slots take FFT_F16 or FFT_F32.
+ */
+typedef enum { FFT_F16 = 0, FFT_F32 = 1, FFT_F16_F32 = 2 } fft_dtype;
 
 /*
  * Twiddle-table kind (Sec. II-III):

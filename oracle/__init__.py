@@ -15,7 +15,9 @@ gcc into ``oracle/_liboracle.so``:
   of eqs. (std1)-(std2));
 * ``emulate_f16`` / ``emulate_f32`` / ``emulate_f64``: the radix-2 Stockham pass
   order with every butterfly as the six FMAs of eqs. (berg-s)-(berg-B) or
-  (lf-s)-(lf-B), each FMA rounded once to the working precision;
+  (lf-s)-(lf-B), each FMA rounded once to the working precision (and
+  ``emulate(..., "f16f32")``: binary16 data, binary32 butterflies, one rounding
+  of each result to binary16);
 * ``errors``: relative L2, max-abs (complex modulus) and non-finite count;
 * ``analytic_bounds``: per-butterfly and cumulative bounds of eqs.
   (per-butterfly-error) and (cumulative), as printed in Tables I-II.
@@ -146,9 +148,18 @@ def emulate(x: np.ndarray, kind="dual_select", prec: str = "f16", inverse: bool 
 
     ``x`` holds values of the working precision: float16 for "f16", float32 for
     "f32", float64 for "f64"; the result has the same dtype.
+
+    "f16f32" (binary16 storage, binary32 butterflies): ``x`` holds float16
+    values; they are widened exactly to binary32, transformed with every FMA
+    rounded once to binary32 and the binary32 table, and each result is
+    rounded once to binary16 (round to nearest even).
     """
     lib = _load()
     inv = int(inverse)
+    if prec == "f16f32":
+        x16 = _as_batch(x, np.float16)
+        y32 = emulate(x16.astype(np.float32), kind, "f32", inverse)
+        return rn16(y32.astype(np.float64)).reshape(y32.shape)
     if prec == "f16":
         x = _as_batch(x, np.float16)
         out = np.empty_like(x)

@@ -19,9 +19,10 @@ HEADER = os.path.join(os.path.dirname(_HERE), "include", "dsfft.h")
 
 FFT_OK, FFT_EINVAL, FFT_ENOMEM, FFT_EHIP, FFT_EUNSUPPORTED = 0, -1, -2, -3, -4
 FFT_F16, FFT_F32 = 0, 1
-DTYPES = {"f16": FFT_F16, "f32": FFT_F32}
+FFT_F16_F32 = 2           # binary16 storage, binary32 butterflies (plans only)
+DTYPES = {"f16": FFT_F16, "f32": FFT_F32, "f16f32": FFT_F16_F32}
 KINDS = {"dual_select": 0, "linzer_feig": 1, "cosine": 2, "lf_w0_exempt": 3}
-ELEM_BYTES = {FFT_F16: 4, FFT_F32: 8}
+ELEM_BYTES = {FFT_F16: 4, FFT_F32: 8, FFT_F16_F32: 4}
 
 
 class FFTError(RuntimeError):
@@ -303,13 +304,14 @@ def _torch_stream(stream) -> int:
 
 def _check_tensor(t, n: int, batch: int, dt: int):
     import torch
-    want = torch.float16 if dt == FFT_F16 else torch.float32
+    f16_stored = dt in (FFT_F16, FFT_F16_F32)
+    want = torch.float16 if f16_stored else torch.float32
     if not t.is_cuda:
         raise ValueError("tensor must be on the GPU")
     if not t.is_contiguous():
         raise ValueError("tensor must be contiguous")
     ok_dtype = t.dtype == want or (dt == FFT_F32 and t.dtype == torch.complex64) or \
-        (dt == FFT_F16 and t.dtype == torch.complex32)
+        (f16_stored and t.dtype == torch.complex32)
     if not ok_dtype:
         raise ValueError(f"tensor dtype {t.dtype} does not match the plan")
     if t.numel() * t.element_size() != n * batch * ELEM_BYTES[dt]:

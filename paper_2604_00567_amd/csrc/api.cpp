@@ -84,7 +84,8 @@ int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<Devi
 // ------------------------------------------------------------ kernel choice
 
 static const KernelCfg* table_for(int dtype, int* count) {
-    return dtype == DT_F16 ? kernel_table_f16(count) : kernel_table_f32(count);
+    return dtype == DT_F16 ? kernel_table_f16(count)
+                           : (dtype == DT_F32 ? kernel_table_f32(count) : kernel_table_f16f32(count));
 }
 
 const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant) {
@@ -154,7 +155,10 @@ int choose_schedule(fft_plan* p, const int* variants) {
     return FFT_OK;
 }
 
-int elem_bytes(int dtype) { return dtype == DT_F16 ? 4 : 8; }
+// Bytes of a stored element (the plan's input and output) and of a two-pass
+// intermediate element (the compute precision).
+int elem_bytes(int dtype) { return dtype == DT_F32 ? 8 : 4; }
+int work_elem_bytes(int dtype) { return dtype == DT_F16 ? 4 : 8; }
 
 // Workspace: two-pass schedules stage the intermediate per chunk of
 // transforms, capped at 128 MiB (measured: 128 MiB chunks run 5-6 % faster
@@ -166,7 +170,7 @@ void size_workspace(fft_plan* p) {
         p->ws_need = 0;
         return;
     }
-    const size_t per = (size_t)p->n * elem_bytes(p->dtype);
+    const size_t per = (size_t)p->n * work_elem_bytes(p->dtype);
     const size_t cap = (size_t)128 << 20;
     int64_t chunk = (int64_t)std::max<size_t>(1, cap / per);
     chunk = std::min<int64_t>(chunk, p->batch);
@@ -209,8 +213,8 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
         set_error(FFT_EINVAL, "batch must be >= 1");
         return nullptr;
     }
-    if (dtype != DT_F16 && dtype != DT_F32) {
-        set_error(FFT_EINVAL, "dtype must be FFT_F16 or FFT_F32");
+    if (dtype != DT_F16 && dtype != DT_F32 && dtype != DT_F16F32) {
+        set_error(FFT_EINVAL, "dtype must be FFT_F16, FFT_F32 or FFT_F16_F32");
         return nullptr;
     }
     if (kind < 0 || kind > 3) {
@@ -230,7 +234,7 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
         hip_error(e, "hipGetDevice");
         return nullptr;
     }
-    if (get_table(n, dtype, kind, inverse, &p->table) != FFT_OK) return nullptr;
+    if (get_table(n, table_dtype(dtype), kind, inverse, &p->table) != FFT_OK) return nullptr;
     int tuned[3];
     if (!variants && tuned_choice(dtype, p->log_n, tuned)) {
         // a recorded tuning choice; fall back to the fixed rule if it no longer exists

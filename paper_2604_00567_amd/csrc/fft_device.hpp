@@ -98,6 +98,43 @@ template <class E> struct TwOf;
 template <> struct TwOf<uint32_t> { using type = TwH; };
 template <> struct TwOf<f2_t> { using type = TwF; };
 
+// Storage and compute types.  A kernel computes in E; its input and output
+// may be stored in another type S (binary16 storage with binary32
+// butterflies: S = binary16 pair, E = binary32 pair).  Loads widen exactly,
+// stores round once, to nearest even; with S = E both are the identity.
+__device__ __forceinline__ uint32_t to_storage(uint32_t v, uint32_t) { return v; }
+__device__ __forceinline__ f2_t to_storage(f2_t v, f2_t) { return v; }
+// One v_cvt_f16_f32 per half (rounding by the mode register: to nearest
+// even).  The compiler would otherwise pair the two halves into
+// v_cvt_pk_f16_f32, which on gfx950 resolved exact ties to the odd
+// neighbour in testing, not to the even one.
+__device__ __forceinline__ uint32_t to_storage(f2_t v, uint32_t) {
+    const float x = v.x, y = v.y;
+    uint32_t lo, hi;
+    asm("v_cvt_f16_f32 %0, %1" : "=v"(lo) : "v"(x));
+    asm("v_cvt_f16_f32 %0, %1" : "=v"(hi) : "v"(y));
+    return (lo & 0xffffu) | (hi << 16);
+}
+__device__ __forceinline__ uint32_t to_compute(uint32_t s, uint32_t) { return s; }
+__device__ __forceinline__ f2_t to_compute(f2_t s, f2_t) { return s; }
+__device__ __forceinline__ f2_t to_compute(uint32_t s, f2_t) {
+    const h2_t h = as_h2(s);
+    f2_t v;
+    v.x = (float)h.x;
+    v.y = (float)h.y;
+    return v;
+}
+template <class E, class S>
+__device__ __forceinline__ E load_elem(const S* p, bool stream) {
+    return to_compute(stream ? __builtin_nontemporal_load(p) : *p, E{});
+}
+template <class E, class S>
+__device__ __forceinline__ void store_elem(E v, S* p, bool stream) {
+    const S s = to_storage(v, S{});
+    if (stream) __builtin_nontemporal_store(s, p);
+    else *p = s;
+}
+
 // Level-ordered twiddle table: entry L/2 + j is T_L[j] = W_L^j for span L (a
 // power of two) and j < L/2, stored as TwH/TwF.  Since theta = -(2 pi j)/L
 // scales exactly by powers of two, T_L[j] equals T_N[j N / L] bit for bit, so
@@ -371,8 +408,8 @@ using GridGeo = GridGeoT<false>;
 // group r = g + G u (residue r, span 1) takes elements r + M i, i < R.
 // The streaming hint is used only where a wave's accesses cover whole lines.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int LANE,
-          class Geo>
-__device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
+          class Geo, class SI>
+__device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NU = 1 << LOG_NU;
     constexpr int EL = 1 << LOG_E;
@@ -395,8 +432,7 @@ __device__ __forceinline__ void load_pass0(E* v, const E* in, const Geo& gp) {
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int64_t idx = r + (int64_t)M * i;
-                    const E* src = in + geo.base_in + idx * geo.in_stride;
-                    vk[u * R + i] = (MODE != MODE_COLS) ? __builtin_nontemporal_load(src) : *src;
+                    vk[u * R + i] = load_elem<E>(in + geo.base_in + idx * geo.in_stride, MODE != MODE_COLS);
                 }
             }
         } else {
@@ -473,9 +509,9 @@ __device__ __forceinline__ void pin_twiddle(TwF& t) {
 // LR radix-2 stages per group, scatter (LDS or global).  twp: this pass's
 // twiddles when the previous pass loaded them (twiddle_prefetch).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PRE, int P, class Geo>
+          int LANE, int PRE, int P, class Geo, class SI, class SO>
 __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
-                                          const E* in, E* out, const Geo& gp,
+                                          const SI* in, SO* out, const Geo& gp,
                                           const typename TwOf<E>::type* twp = nullptr) {
     using TW = typename TwOf<E>::type;
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
@@ -495,6 +531,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
         static_assert(UPL == 1 || (MODE == MODE_SMALL && !LANE && UPW % UPL == 0),
                       "several units per lane: whole-transform units without the lane tail");
+        static_assert(!STG || (sizeof(SI) == sizeof(E) && sizeof(SO) == sizeof(E)),
+                      "16-byte staging copies stored values unchanged");
         constexpr int XR = exchange_rounds<E, LOG_E, MODE, UPW, PP>();
         static_assert(XR == 1 || (UPL == 1 && !LANE && !STG && PRE == 0),
                       "two-round exchanges: one plain unit per workgroup");
@@ -602,8 +640,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                 for (int k = 0; k < EL / 2; ++k) {
                     const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
-                    __builtin_nontemporal_store(v[2 * k], out + geo0.base_out + jb);
-                    __builtin_nontemporal_store(v[2 * k + 1], out + geo0.base_out + jb + NU / 2);
+                    store_elem(v[2 * k], out + geo0.base_out + jb, true);
+                    store_elem(v[2 * k + 1], out + geo0.base_out + jb + NU / 2, true);
                 }
             }
         } else if constexpr (P + 1 < NP && XR == 2) {
@@ -694,9 +732,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                         for (int e = 0; e < R; ++e) {
                             const int64_t idx = q + (int64_t)L0 * e;
-                            E* dst = out + geo.base_out + idx * geo.out_stride;
-                            if (MODE == MODE_SMALL) __builtin_nontemporal_store(v[k * EL + u * R + e], dst);
-                            else *dst = v[k * EL + u * R + e];
+                            store_elem(v[k * EL + u * R + e], out + geo.base_out + idx * geo.out_stride,
+                                       MODE == MODE_SMALL);
                         }
                     }
                 }
@@ -712,34 +749,36 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
-__device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
+          int LANE, int PIPE, class SI, class SO>
+__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
                                                  int64_t units, int log_m);
 
+// SI, SO: storage types of the input and output (E unless the plan stores
+// binary16 and computes in binary32).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+          int LANE, int PIPE, class SI = E, class SO = E>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E))
-fft_unit_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
+fft_unit_kernel(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
-                                                                                  units, log_m);
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO>(
+        in, out, lt, units, log_m);
 }
 
 // The pipelined kernel holds two register sets; the compiler is asked to fit
 // three waves per SIMD so the prefetch is not bought with occupancy.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+          int LANE, int PIPE, class SI = E, class SO = E>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
-fft_unit_kernel_pipe(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
+fft_unit_kernel_pipe(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
                      int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>(in, out, lt,
-                                                                                  units, log_m);
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO>(
+        in, out, lt, units, log_m);
 }
 
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
-__device__ __forceinline__ void unit_kernel_body(const E* in, E* out,
+          int LANE, int PIPE, class SI, class SO>
+__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
                                                  int64_t units, int log_m) {
     static_assert(LR0 + LR1 + LR2 + 2 * LANE == LOG_NU, "radices must multiply to NU");

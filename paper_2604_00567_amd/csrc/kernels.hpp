@@ -12,7 +12,7 @@ typedef hipError_t (*LaunchFn)(const void* in, void* out, const void* lt, int64_
                                int log_m, hipStream_t stream);
 
 struct KernelCfg {
-    int dtype;      // DT_F16 / DT_F32
+    int dtype;      // DT_F16 / DT_F32 / DT_F16F32
     int mode;       // MODE_SMALL / MODE_COLS / MODE_ROWS
     int log_nu;     // unit size (log2)
     int log_e;      // elements per lane and unit (log2)
@@ -32,5 +32,6 @@ struct KernelCfg {
 // All configurations for one dtype, in order of preference per (mode, log_nu).
 const KernelCfg* kernel_table_f16(int* count);
 const KernelCfg* kernel_table_f32(int* count);
+const KernelCfg* kernel_table_f16f32(int* count);
 
 }  // namespace dsfft

@@ -1,83 +1,110 @@
 // Instantiates every configuration of configs.inc for one element type
-// (included by kernels_f16.hip / kernels_f32.hip with ELEM_T, DTYPE_ID, TABLE_FN).
+// (included by kernels_f16.hip / kernels_f32.hip / kernels_f16f32.hip with
+// ELEM_T (compute type), STORE_T (storage type of the plan's input and
+// output, ELEM_T if not defined), DTYPE_ID and TABLE_FN).
+#include <type_traits>
+
 #include "fft_device.hpp"
 #include "kernels.hpp"
 #include "tables.hpp"
 
+#ifndef STORE_T
+#define STORE_T ELEM_T
+#endif
+
 namespace dsfft {
 
-// Whether the configuration fits a workgroup's LDS with element type E.
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int LANE>
+// Input and output storage of a kernel computing in E for a plan stored in
+// S: whole transforms read and write S; the two-pass schedule keeps its
+// intermediate in E (columns read S and write E, rows read E and write S).
+template <class E, class S, int MODE>
+struct IoOf {
+    using in = std::conditional_t<MODE == MODE_ROWS, E, S>;
+    using out = std::conditional_t<MODE == MODE_COLS, E, S>;
+};
+
+// Whether a configuration is compiled for (E, S): it fits a workgroup's LDS,
+// and with S != E it is neither staged (16-byte copies move stored values
+// unchanged) nor pipelined.
+template <class E, class S, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
+          int LANE, int PIPE>
 static constexpr bool cfg_fits() {
+    if constexpr (!std::is_same_v<E, S>)
+        if (STG || PIPE == 1) return false;
     return unit_fits<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
 }
 
 // The kernel of a configuration: the pipelined entry (with its occupancy
 // attribute) only where PIPE = 1.
-template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
+          int STG, int LANE, int PIPE>
 static constexpr auto kernel_ptr() {
+    using IO = IoOf<E, S, MODE>;
     if constexpr (PIPE == 1)
-        return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
+        return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE,
+                                     typename IO::in, typename IO::out>;
     else
-        return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>;
+        return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE,
+                                typename IO::in, typename IO::out>;
 }
 
-// Its entry for the registry; none for a configuration that does not fit
-// (that kernel is not instantiated).
-template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+// Its entry for the registry; none for a configuration that is not compiled.
+template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
+          int STG, int LANE, int PIPE>
 static constexpr const void* kernel_entry() {
-    if constexpr (!cfg_fits<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>())
+    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>())
         return nullptr;
     else
-        return (const void*)kernel_ptr<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+        return (const void*)kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
 }
 
-template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
+          int STG, int LANE, int PIPE>
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
     using TW = typename TwOf<E>::type;
-    if constexpr (!cfg_fits<E, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>()) {
+    using IO = IoOf<E, S, MODE>;
+    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()) {
         return hipErrorInvalidConfiguration;
     } else {
-    constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
-    constexpr size_t LDS =
-        unit_lds_elems<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() * sizeof(E);
-    auto kern = kernel_ptr<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
-    int64_t grid = (units + UPW - 1) / UPW;
-    if (grid <= 0) return hipSuccess;
-    if (PIPE == 1) {
-        // persistent grid: the workgroups that fit on the device at once
-        static int resident = 0;
-        if (!resident) {
-            int dev = 0, cus = 0, per = 0;
-            if (hipGetDevice(&dev) != hipSuccess ||
-                hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, NT, LDS) != hipSuccess)
-                return hipErrorInvalidConfiguration;
-            resident = cus * (per > 0 ? per : 1);
+        constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
+        constexpr size_t LDS =
+            unit_lds_elems<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() * sizeof(E);
+        auto kern = kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+        int64_t grid = (units + UPW - 1) / UPW;
+        if (grid <= 0) return hipSuccess;
+        if (PIPE == 1) {
+            // persistent grid: the workgroups that fit on the device at once
+            static int resident = 0;
+            if (!resident) {
+                int dev = 0, cus = 0, per = 0;
+                if (hipGetDevice(&dev) != hipSuccess ||
+                    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                    hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, NT, LDS) != hipSuccess)
+                    return hipErrorInvalidConfiguration;
+                resident = cus * (per > 0 ? per : 1);
+            }
+            grid = grid < resident ? grid : resident;
         }
-        grid = grid < resident ? grid : resident;
-    }
-    if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), LDS, stream, (const E*)in, (E*)out,
-                       (const TW*)lt, units, log_m);
-    return hipGetLastError();
+        if (grid > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(NT), LDS, stream, (const typename IO::in*)in,
+                           (typename IO::out*)out, (const TW*)lt, units, log_m);
+        return hipGetLastError();
     }
 }
 
-// An entry that does not fit gets mode -1: no plan or tuner ever selects it.
+// An entry that is not compiled gets mode -1: no plan or tuner ever selects it.
 #define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \
     {DTYPE_ID,                                                                                 \
-     cfg_fits<ELEM_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, LANE>() ? (MODE) : -1,          \
+     cfg_fits<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()      \
+         ? (MODE)                                                                              \
+         : -1,                                                                                 \
      LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE,                                 \
      ((UPW) / (UPL)) << ((LOG_NU) - (LOG_E)),                                                  \
      unit_lds_elems<ELEM_T, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() *        \
          sizeof(ELEM_T),                                                                       \
-     &launch_unit<ELEM_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>,      \
-     kernel_entry<ELEM_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()},
+     &launch_unit<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>, \
+     kernel_entry<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()},
 #define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE)                          \
     CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, 1)
 

@@ -25,6 +25,7 @@ const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant);
 int count_kernels(int dtype, int mode, int log_nu);
 std::string describe(const KernelCfg* k);
 int elem_bytes(int dtype);
+int work_elem_bytes(int dtype);
 
 }  // namespace dsfft
 

@@ -8,7 +8,10 @@
 
 namespace dsfft {
 
-enum { DT_F16 = 0, DT_F32 = 1 };
+// DT_F16F32: binary16 storage, binary32 butterflies and table.
+enum { DT_F16 = 0, DT_F32 = 1, DT_F16F32 = 2 };
+// The table (and arithmetic) precision of a plan dtype.
+inline int table_dtype(int dtype) { return dtype == DT_F16 ? DT_F16 : DT_F32; }
 enum { TABLE_DUAL_SELECT = 0, TABLE_LINZER_FEIG = 1, TABLE_COSINE = 2, TABLE_LF_W0_EXEMPT = 3 };
 
 struct Twiddle64 {

@@ -104,10 +104,10 @@ static void store_record(int dtype, int log_n, const TuneRec& r) {
 }
 
 // Deterministic synthetic data in [-1, 1): a 64-bit LCG, rounded to the
-// storage precision.
+// storage precision (binary16 for both binary16-stored dtypes).
 static void fill_synthetic(std::vector<uint8_t>& buf, int dtype, uint64_t seed) {
     uint64_t s = seed * 6364136223846793005ULL + 1442695040888963407ULL;
-    if (dtype == DT_F16) {
+    if (dtype != DT_F32) {
         uint16_t* p = (uint16_t*)buf.data();
         for (size_t i = 0; i < buf.size() / 2; ++i) {
             s = s * 6364136223846793005ULL + 1442695040888963407ULL;

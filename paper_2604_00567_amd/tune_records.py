@@ -1,7 +1,7 @@
 """Generates tuning records for this device: runs the library's autotuner
 (fft_tune: every compiled configuration timed with HIP events, only outputs
 bit-identical to the default configuration accepted) for N = 2^1 .. 2^20 in
-both precisions and appends the winners to --out (the DSFFT_TUNE_FILE
+each precision and appends the winners to --out (the DSFFT_TUNE_FILE
 format).  Copy the file beside libdsfft.so as tuning_records.txt to make the
 records the library's defaults.
 
@@ -23,12 +23,15 @@ def main():
     ap.add_argument("--reps", type=int, default=10)
     ap.add_argument("--log-min", type=int, default=1)
     ap.add_argument("--log-max", type=int, default=20)
+    ap.add_argument("--dtypes", default="f16,f32,f16f32",
+                    help="comma-separated: f16, f32, f16f32 (binary16 storage, binary32 butterflies)")
     args = ap.parse_args()
     os.environ["DSFFT_TUNE_FILE"] = os.path.abspath(args.out)
     from paper_2604_00567_amd import binding
 
-    for dtype in ("f16", "f32"):
-        eb = 4 if dtype == "f16" else 8
+    ap_dtypes = args.dtypes.split(",")
+    for dtype in ap_dtypes:
+        eb = 8 if dtype == "f32" else 4
         for m in range(args.log_min, args.log_max + 1):
             n = 1 << m
             batch = max(1, int(args.bytes // (n * eb)))
