@@ -124,14 +124,17 @@ __device__ __forceinline__ f2_t to_compute(uint32_t s, f2_t) {
     v.y = (float)h.y;
     return v;
 }
-template <class E, class S>
-__device__ __forceinline__ E load_elem(const S* p, bool stream) {
-    return to_compute(stream ? __builtin_nontemporal_load(p) : *p, E{});
+// STREAM: the streaming (non-temporal) hint; a compile-time choice, so that
+// each access is emitted in exactly one form.
+template <bool STREAM, class E, class S>
+__device__ __forceinline__ E load_elem(const S* p) {
+    if constexpr (STREAM) return to_compute(__builtin_nontemporal_load(p), E{});
+    else return to_compute(*p, E{});
 }
-template <class E, class S>
-__device__ __forceinline__ void store_elem(E v, S* p, bool stream) {
+template <bool STREAM, class E, class S>
+__device__ __forceinline__ void store_elem(E v, S* p) {
     const S s = to_storage(v, S{});
-    if (stream) __builtin_nontemporal_store(s, p);
+    if constexpr (STREAM) __builtin_nontemporal_store(s, p);
     else *p = s;
 }
 
@@ -432,7 +435,7 @@ __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int64_t idx = r + (int64_t)M * i;
-                    vk[u * R + i] = load_elem<E>(in + geo.base_in + idx * geo.in_stride, MODE != MODE_COLS);
+                    vk[u * R + i] = load_elem<MODE != MODE_COLS, E>(in + geo.base_in + idx * geo.in_stride);
                 }
             }
         } else {
@@ -640,8 +643,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                 for (int k = 0; k < EL / 2; ++k) {
                     const int jb = q + 16 * (2 * k + u) + (NU / 4) * r;
-                    store_elem(v[2 * k], out + geo0.base_out + jb, true);
-                    store_elem(v[2 * k + 1], out + geo0.base_out + jb + NU / 2, true);
+                    store_elem<true>(v[2 * k], out + geo0.base_out + jb);
+                    store_elem<true>(v[2 * k + 1], out + geo0.base_out + jb + NU / 2);
                 }
             }
         } else if constexpr (P + 1 < NP && XR == 2) {
@@ -732,8 +735,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                         for (int e = 0; e < R; ++e) {
                             const int64_t idx = q + (int64_t)L0 * e;
-                            store_elem(v[k * EL + u * R + e], out + geo.base_out + idx * geo.out_stride,
-                                       MODE == MODE_SMALL);
+                            store_elem<MODE == MODE_SMALL>(v[k * EL + u * R + e],
+                                                           out + geo.base_out + idx * geo.out_stride);
                         }
                     }
                 }
