@@ -201,6 +201,33 @@ def run_once(torch, binding, x: np.ndarray, dtype: str, kind: str) -> np.ndarray
     return yt.cpu().numpy()
 
 
+def bench_encodings(torch, binding, xs, ys, n, batch, steps, warmup):
+    """The butterfly's path encodings (table-held operand order, per-lane
+    select, per-lane branch) of the same kernel configurations, timed on the
+    same buffers; all three give bit-identical outputs (parity tests)."""
+    single, _, _ = binding.fft_config_count(n, "f16")
+    by_cfg = {}
+    for v in range(single):
+        p = binding.Plan(n, batch, "f16", "dual_select", variant=(v, 0, False))
+        cfg = p.info()["config"]
+        p.close()
+        base = cfg.replace(",enc=select", "").replace(",enc=branch", "")
+        enc = "select" if ",enc=select" in cfg else ("branch" if ",enc=branch" in cfg else "table")
+        by_cfg.setdefault(base, {})[enc] = v
+    out = {}
+    for base, encs in by_cfg.items():
+        if len(encs) < 3:
+            continue
+        row = {}
+        for enc, v in encs.items():
+            p = binding.Plan(n, batch, "f16", "dual_select", variant=(v, 0, False))
+            _, dev = timed_loop(torch, lambda i: p.execute(xs[i], ys[i]), len(xs), steps, warmup)
+            p.close()
+            row[enc] = {"kernel_ms": round(dev * 1e3, 4), "gbs": round(2.0 * n * batch * 4 / dev / 1e9, 1)}
+        out[base] = row
+    return out
+
+
 def bench_uneven(torch, binding, inputs, steps, warmup):
     sizes = inputs.uneven_sizes(4096, seed=4)
     x0 = inputs.packed_uniform(sizes, 4, "f16")
@@ -418,6 +445,9 @@ def main():
         inv.close()
         result["inverse_n1024"] = {"kernel_ms": round(dev * 1e3, 4),
                                    "gbs": round(2.0 * 1024 * 65536 * 4 / dev / 1e9, 1)}
+        log("path encodings (table, select, branch)")
+        result["encodings_n1024"] = bench_encodings(torch, binding, xs_, ys_, 1024, 65536, args.steps,
+                                                    args.warmup)
         log("binary16 storage, binary32 butterflies")
         mix = binding.Plan(1024, 65536, "f16f32", "dual_select")
         _, dev = timed_loop(torch, lambda i: mix.execute(xs_[i], ys_[i]), len(xs_), args.steps,

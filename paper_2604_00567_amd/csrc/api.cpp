@@ -125,6 +125,7 @@ std::string describe(const KernelCfg* k) {
                   k->staged, k->lane_tail, k->pipelined, k->threads, k->lds_bytes);
     std::string d = buf;
     if (k->upl > 1) d += ",upl=" + std::to_string(k->upl);
+    if (k->encoding) d += k->encoding == 1 ? ",enc=select" : ",enc=branch";
     return d;
 }
 

@@ -94,6 +94,69 @@ __device__ __forceinline__ void bfly(f2_t& a, f2_t& b, const TwF tw) {
     b = B;
 }
 
+// Encodings of the path choice (the select flag of Sec. III; Sec. VI notes
+// that the branch on it can become an operand order held in the table):
+//   ENC_TABLE   the table entry carries the operand order (a rotate amount)
+//               and the multiplier with the path's sign (sigma m, m): no
+//               branch, no select (the form every kernel uses by default);
+//   ENC_SELECT  each lane selects the operand order and the multiplier's
+//               sign from the path flag (v_cndmask);
+//   ENC_BRANCH  each lane branches on the path flag and runs that path's
+//               code (lanes of one wave on both paths run both).
+// All three compute the same FMAs on the same operands (bit-identical);
+// binary16 kernels only (the binary32 butterfly always uses a lane mask).
+enum { ENC_TABLE = 0, ENC_SELECT = 1, ENC_BRANCH = 2 };
+
+template <int ENC>
+__device__ __forceinline__ void bfly_enc(uint32_t& a, uint32_t& b, const TwH tw) {
+    if constexpr (ENC == ENC_TABLE) {
+        bfly(a, b, tw);
+    } else {
+        const bool sine = (tw.ts & 16u) != 0;      // the path flag
+        const h2_t tv = as_h2(tw.ts);
+        const _Float16 m = as_h2(tw.w).y;           // the multiplier, unsigned by path
+        const h2_t av = as_h2(a);
+        h2_t tt;
+        tt.x = -tv.y;
+        tt.y = tv.y;
+        h2_t A, B;
+        if constexpr (ENC == ENC_SELECT) {
+            const uint32_t c = sine ? __builtin_amdgcn_alignbit(b, b, 16) : b;
+            h2_t w;
+            w.x = sine ? -m : m;
+            w.y = m;
+            const h2_t cv = as_h2(c);
+            const h2_t s = __builtin_elementwise_fma(tt, cv.yx, cv);
+            A = __builtin_elementwise_fma(s, w, av);
+            B = __builtin_elementwise_fma(-s, w, av);
+        } else if (sine) {
+            asm volatile("");                        // keeps the branch (no if-conversion)
+            const h2_t cv = as_h2(__builtin_amdgcn_alignbit(b, b, 16));   // (b_i, b_r)
+            h2_t w;
+            w.x = -m;
+            w.y = m;
+            const h2_t s = __builtin_elementwise_fma(tt, cv.yx, cv);
+            A = __builtin_elementwise_fma(s, w, av);
+            B = __builtin_elementwise_fma(-s, w, av);
+        } else {
+            asm volatile("");
+            const h2_t bv = as_h2(b);
+            h2_t w;
+            w.x = m;
+            w.y = m;
+            const h2_t s = __builtin_elementwise_fma(tt, bv.yx, bv);
+            A = __builtin_elementwise_fma(s, w, av);
+            B = __builtin_elementwise_fma(-s, w, av);
+        }
+        a = as_u32(A);
+        b = as_u32(B);
+    }
+}
+template <int ENC>
+__device__ __forceinline__ void bfly_enc(f2_t& a, f2_t& b, const TwF tw) {
+    bfly(a, b, tw);
+}
+
 template <class E> struct TwOf;
 template <> struct TwOf<uint32_t> { using type = TwH; };
 template <> struct TwOf<f2_t> { using type = TwF; };
@@ -150,7 +213,7 @@ __device__ __forceinline__ void store_elem(E v, S* p) {
 // (1..LR) pairs v[i + 2He] with v[i + H + 2He] (H = R >> t, i < H, e < 2^(t-1))
 // under twiddle c = 2^(t-1) + e, and writes A to v[i + He], B to v[i + He + R/2].
 // On entry v[i] = Y[r + M i][q]; on exit v[e] = Y'[r][q + L0 e].
-template <int LR, class E, class TW>
+template <int LR, int ENC = ENC_TABLE, class E, class TW>
 __device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
     constexpr int R = 1 << LR;
 #pragma unroll
@@ -163,7 +226,7 @@ __device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
             for (int i = 0; i < H; ++i) {
                 E a = v[i + 2 * H * e];
                 E b = v[i + H + 2 * H * e];
-                bfly(a, b, tw[(1 << (t - 1)) + e]);
+                bfly_enc<ENC>(a, b, tw[(1 << (t - 1)) + e]);
                 nv[i + H * e] = a;
                 nv[i + H * e + R / 2] = b;
             }
@@ -379,10 +442,12 @@ __device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __
 // Where the units of one workgroup live: a regular launch takes UPW
 // consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
 // units of one work item (BatchGeo, in fft_batch.hpp).
-template <bool TWPF>
+template <bool TWPF, int ENC = ENC_TABLE>
 struct GridGeoT {
     // the next pass's twiddles are loaded a pass ahead (twiddle_prefetch)
     static constexpr bool kTwiddlePrefetch = TWPF;
+    // the butterfly's path encoding (bfly_enc)
+    static constexpr int kEncoding = ENC;
     int64_t ublk, units;
     int log_m;
     int lane_id;       // threadIdx.x (opaque per block in the persistent loop)
@@ -610,7 +675,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
             }
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) reg_pass<LR>(v + k * EL + u * R, tw);
+            for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding>(v + k * EL + u * R, tw);
         }
         if constexpr (PF && P + 1 < NP) {
             // entries c >= 1 of each group are the loaded ones
@@ -752,7 +817,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // the number of columns (MODE_COLS) or rows (MODE_ROWS) per transform; 0 for
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE, class SI, class SO>
+          int LANE, int PIPE, class SI, class SO, int ENC>
 __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
                                                  int64_t units, int log_m);
@@ -760,27 +825,27 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
 // SI, SO: storage types of the input and output (E unless the plan stores
 // binary16 and computes in binary32).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE, class SI = E, class SO = E>
+          int LANE, int PIPE, class SI = E, class SO = E, int ENC = ENC_TABLE>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E))
 fft_unit_kernel(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
                 int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO>(
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO, ENC>(
         in, out, lt, units, log_m);
 }
 
 // The pipelined kernel holds two register sets; the compiler is asked to fit
 // three waves per SIMD so the prefetch is not bought with occupancy.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE, class SI = E, class SO = E>
+          int LANE, int PIPE, class SI = E, class SO = E, int ENC = ENC_TABLE>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
 fft_unit_kernel_pipe(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
                      int64_t units, int log_m) {
-    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO>(
+    unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO, ENC>(
         in, out, lt, units, log_m);
 }
 
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE, class SI, class SO>
+          int LANE, int PIPE, class SI, class SO, int ENC>
 __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
                                                  const typename TwOf<E>::type* __restrict__ lt,
                                                  int64_t units, int log_m) {
@@ -831,7 +896,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             blk += step;
         }
     } else {
-        const GridGeoT<PIPE == 2> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
+        const GridGeoT<PIPE == 2, ENC> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

@@ -23,6 +23,7 @@ struct KernelCfg {
     int lane_tail;  // 1: the last two stages run across lanes (permlane swaps)
     int pipelined;  // 1: persistent workgroups prefetch the next block into registers;
                     // 2: each pass loads the next pass's twiddles
+    int encoding;   // path encoding of the butterfly: 0 table, 1 select, 2 branch
     int threads;    // workgroup size
     size_t lds_bytes;
     LaunchFn launch;

@@ -24,53 +24,58 @@ struct IoOf {
 };
 
 // Whether a configuration is compiled for (E, S): it fits a workgroup's LDS,
-// and with S != E it is neither staged (16-byte copies move stored values
-// unchanged) nor pipelined.
+// with S != E it is neither staged (16-byte copies move stored values
+// unchanged) nor pipelined, and a path encoding other than the table's is a
+// binary16 variant of a plain kernel.
 template <class E, class S, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
-          int LANE, int PIPE>
+          int LANE, int PIPE, int ENC>
 static constexpr bool cfg_fits() {
     if constexpr (!std::is_same_v<E, S>)
         if (STG || PIPE == 1) return false;
+    // the path-encoding variants: binary16 plans, plain (non-pipelined, no lane tail) kernels
+    if (ENC != ENC_TABLE && (!std::is_same_v<E, uint32_t> || !std::is_same_v<E, S> || PIPE == 1 || LANE))
+        return false;
     return unit_fits<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
 }
 
 // The kernel of a configuration: the pipelined entry (with its occupancy
 // attribute) only where PIPE = 1.
 template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
-          int STG, int LANE, int PIPE>
+          int STG, int LANE, int PIPE, int ENC>
 static constexpr auto kernel_ptr() {
     using IO = IoOf<E, S, MODE>;
     if constexpr (PIPE == 1)
         return &fft_unit_kernel_pipe<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE,
-                                     typename IO::in, typename IO::out>;
+                                     typename IO::in, typename IO::out, ENC>;
     else
         return &fft_unit_kernel<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE,
-                                typename IO::in, typename IO::out>;
+                                typename IO::in, typename IO::out, ENC>;
 }
 
 // Its entry for the registry; none for a configuration that is not compiled.
 template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
-          int STG, int LANE, int PIPE>
+          int STG, int LANE, int PIPE, int ENC>
 static constexpr const void* kernel_entry() {
-    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>())
+    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>())
         return nullptr;
     else
-        return (const void*)kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+        return (const void*)kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE,
+                                       ENC>();
 }
 
 template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2,
-          int STG, int LANE, int PIPE>
+          int STG, int LANE, int PIPE, int ENC>
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
     using TW = typename TwOf<E>::type;
     using IO = IoOf<E, S, MODE>;
-    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()) {
+    if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>()) {
         return hipErrorInvalidConfiguration;
     } else {
         constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
         constexpr size_t LDS =
             unit_lds_elems<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() * sizeof(E);
-        auto kern = kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>();
+        auto kern = kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>();
         int64_t grid = (units + UPW - 1) / UPW;
         if (grid <= 0) return hipSuccess;
         if (PIPE == 1) {
@@ -94,17 +99,19 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
 }
 
 // An entry that is not compiled gets mode -1: no plan or tuner ever selects it.
-#define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \
+#define CFGE(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL, ENC)              \
     {DTYPE_ID,                                                                                 \
-     cfg_fits<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()      \
+     cfg_fits<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>() \
          ? (MODE)                                                                              \
          : -1,                                                                                 \
-     LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE,                                 \
+     LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE, ENC,                            \
      ((UPW) / (UPL)) << ((LOG_NU) - (LOG_E)),                                                  \
      unit_lds_elems<ELEM_T, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() *        \
          sizeof(ELEM_T),                                                                       \
-     &launch_unit<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>, \
-     kernel_entry<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE>()},
+     &launch_unit<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>, \
+     kernel_entry<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>()},
+#define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \
+    CFGE(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL, ENC_TABLE)
 #define CFG(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE)                          \
     CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, 1)
 
@@ -113,6 +120,7 @@ static const KernelCfg kTable[] = {
 };
 #undef CFG
 #undef CFGU
+#undef CFGE
 
 const KernelCfg* TABLE_FN(int* count) {
     *count = (int)(sizeof(kTable) / sizeof(kTable[0]));

@@ -21,12 +21,14 @@ MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
 def load_configs(with_upl=False):
     out = []
     for line in open(CONFIGS):
-        m = re.match(r"\s*CFG(U?)\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
-                     r"\s*(\d+),\s*(\d+),\s*(\d+)(?:,\s*(\d+))?\)", line)
+        # CFG(10 fields), CFGU(..., UPL), CFGE(..., UPL, ENC); the path
+        # encoding changes no index
+        m = re.match(r"\s*CFG(U|E)?\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
+                     r"\s*(\d+),\s*(\d+),\s*(\d+)(?:,\s*(\d+))?(?:,\s*(ENC_\w+))?\)", line)
         if m:
             mode = MODES[m.group(2)]
             upl = int(m.group(12)) if m.group(1) else 1
-            assert (upl != 1) == bool(m.group(1)) or upl == 1
+            assert (m.group(1) == "E") == (m.group(13) is not None)
             # the pipelined flag changes which workgroup takes a block, not a
             # block's index math (blocks b, b + grid, ... cover every block once)
             cfg = (mode,) + tuple(int(m.group(i)) for i in range(3, 11))
@@ -354,7 +356,7 @@ def test_small_configs_index_math(cfg):
 def test_configs_parsed():
     cfgs = load_configs()
     text = open(CONFIGS).read()
-    assert len(cfgs) == text.count("\nCFG(") + text.count("\nCFGU(") and len(cfgs) > 40
+    assert len(cfgs) == text.count("\nCFG(") + text.count("\nCFGU(") + text.count("\nCFGE(") and len(cfgs) > 40
 
 
 def lane_units(tid, G, upw, upl):
