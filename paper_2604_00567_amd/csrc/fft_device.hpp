@@ -293,12 +293,41 @@ constexpr size_t unit_lds_elems() {
     return exchange_rounds<E, LOG_E, MODE, UPW, PP>() == 2 ? (size_t)PP::half_region()
                                                            : (size_t)UPW * PP::region();
 }
+// Twiddles of the middle pass held in LDS (configurations with PIPE = 3).
+// In a whole-transform unit of three register passes, pass 1 (span L0 before
+// it, radix R) takes for group column q < L0 the entries q + L0 c of the
+// level-ordered table, 1 <= c < R: together the contiguous entries
+// [L0, L0 R).  The workgroup copies them into LDS once, after the exchange
+// area, and pass 1 reads them there instead of through the vector memory
+// path (its lanes read the same L0 (R - 1) entries over and over).  Passes
+// whose column is the same across a wave load through the scalar cache
+// instead (group_twiddles), and take no LDS copy.
+template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP>
+constexpr int lds_twiddle_entries() {
+    if (MODE != MODE_SMALL || LANE || PP::NP != 3) return 0;
+    constexpr int G = (1 << LOG_NU) >> LOG_E;
+    if (PP::log_m(1) >= 6 && G % 64 == 0) return 0;
+    return (1 << (PP::log_l0(1) + PP::lr(1))) - (1 << PP::log_l0(1));
+}
+// Byte offset of the twiddle copy: the exchange area rounded up to 16 bytes.
+template <class E, int LOG_E, int MODE, int UPW, class PP>
+constexpr size_t lds_twiddle_offset() {
+    return (unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) + 15) / 16 * 16;
+}
+// LDS bytes of a workgroup: the exchange area, and with PIPE = 3 the twiddle copy.
+template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
+constexpr size_t unit_lds_bytes() {
+    constexpr int TE = PIPE == 3 ? lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() : 0;
+    if (TE == 0) return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E);
+    return lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>() + (size_t)TE * sizeof(typename TwOf<E>::type);
+}
 // Whether a configuration fits a workgroup's LDS for element type E (the
 // configuration list serves both element sizes; entries that do not fit are
-// neither compiled nor offered).
-template <class E, int LOG_E, int MODE, int UPW, class PP>
+// neither compiled nor offered).  PIPE = 3 also needs a middle pass to serve.
+template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr bool unit_fits() {
-    return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) <= kLdsBytes;
+    if (PIPE == 3 && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() == 0) return false;
+    return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP>() <= kLdsBytes;
 }
 
 // ------------------------------------------------------------------ the kernel
@@ -442,10 +471,12 @@ __device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __
 // Where the units of one workgroup live: a regular launch takes UPW
 // consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
 // units of one work item (BatchGeo, in fft_batch.hpp).
-template <bool TWPF, int ENC = ENC_TABLE>
+template <bool TWPF, int ENC = ENC_TABLE, bool TWL = false>
 struct GridGeoT {
     // the next pass's twiddles are loaded a pass ahead (twiddle_prefetch)
     static constexpr bool kTwiddlePrefetch = TWPF;
+    // the middle pass reads its twiddles from an LDS copy (lds_twiddle_entries)
+    static constexpr bool kTwiddleLds = TWL;
     // the butterfly's path encoding (bfly_enc)
     static constexpr int kEncoding = ENC;
     int64_t ublk, units;
@@ -529,6 +560,14 @@ __device__ __forceinline__ void group_twiddles(typename TwOf<E>::type* tw,
     if constexpr (P == 0 && MODE != MODE_ROWS) {
 #pragma unroll
         for (int c = 1; c < R; ++c) tw[c] = lt[c];
+    } else if constexpr (MODE == MODE_SMALL && !LANE && LOGM >= 6 && G % 64 == 0) {
+        // A wave's 64 lanes hold 64 consecutive groups (g = tid mod G, G a
+        // multiple of 64), and with M >= 64 groups per column they share the
+        // column q: the entries are wave-uniform and load through the scalar
+        // cache, which keeps them off the vector memory path.
+        const int qs = __builtin_amdgcn_readfirstlane(q);
+#pragma unroll
+        for (int c = 1; c < R; ++c) tw[c] = lt[qs + L0 * c];
     } else {
         const int qg = geo0.q0 + (q << geo0.log_lb);
         const int lg0 = L0 << geo0.log_lb;
@@ -665,12 +704,21 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
+        constexpr bool TWL = Geo::kTwiddleLds && P == 1 &&
+                             lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() > 0;
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
             TW tw[R];
             if constexpr (PF && P > 0) {
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = twp[u * R + c];
+            } else if constexpr (TWL) {
+                // entry q + L0 c of the table sits at q + L0 (c - 1) of the copy
+                const TW* ltw = reinterpret_cast<const TW*>(reinterpret_cast<const unsigned char*>(lds) +
+                                                            lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>());
+                const int q = (g + G * u) >> LOGM;
+#pragma unroll
+                for (int c = 1; c < R; ++c) tw[c] = ltw[q + L0 * (c - 1)];
             } else {
                 group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
             }
@@ -857,6 +905,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
     static_assert(PIPE != 2 || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
+    static_assert(PIPE != 3 || MODE == MODE_SMALL, "LDS twiddles need whole-transform units");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
@@ -896,7 +945,23 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             blk += step;
         }
     } else {
-        const GridGeoT<PIPE == 2, ENC> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
+        if constexpr (PIPE == 3) {
+            // copy table entries [L0, L0 R) of the middle pass into LDS after
+            // the exchange area, 16 bytes per lane per step; the barrier after
+            // the first exchange's writes orders it before pass 1 reads it
+            using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+            using TW = typename TwOf<E>::type;
+            constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PPT>();
+            constexpr int CHUNKS = (int)(TE * sizeof(TW) / 16);
+            constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
+            static_assert(TE > 0 && (TE * sizeof(TW)) % 16 == 0 && ((1 << LR0) * sizeof(TW)) % 16 == 0,
+                          "LDS twiddles: whole 16-byte chunks from a 16-byte aligned start");
+            const uint4* src = reinterpret_cast<const uint4*>(lt + (1 << LR0));
+            uint4* dst = reinterpret_cast<uint4*>(lds_raw + lds_twiddle_offset<E, LOG_E, MODE, UPW, PPT>());
+            for (int i = (int)threadIdx.x; i < CHUNKS; i += NT) dst[i] = src[i];
+        }
+        const GridGeoT<PIPE == 2, ENC, PIPE == 3> gp{(int64_t)blockIdx.x * UPW, units, log_m,
+                                                     (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

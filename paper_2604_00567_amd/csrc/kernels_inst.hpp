@@ -35,7 +35,7 @@ static constexpr bool cfg_fits() {
     // the path-encoding variants: binary16 plans, plain (non-pipelined, no lane tail) kernels
     if (ENC != ENC_TABLE && (!std::is_same_v<E, uint32_t> || !std::is_same_v<E, S> || PIPE == 1 || LANE))
         return false;
-    return unit_fits<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
+    return unit_fits<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
 }
 
 // The kernel of a configuration: the pipelined entry (with its occupancy
@@ -74,7 +74,7 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
     } else {
         constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
         constexpr size_t LDS =
-            unit_lds_elems<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() * sizeof(E);
+            unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
         auto kern = kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>();
         int64_t grid = (units + UPW - 1) / UPW;
         if (grid <= 0) return hipSuccess;
@@ -106,8 +106,8 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
          : -1,                                                                                 \
      LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE, ENC,                            \
      ((UPW) / (UPL)) << ((LOG_NU) - (LOG_E)),                                                  \
-     unit_lds_elems<ELEM_T, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() *        \
-         sizeof(ELEM_T),                                                                       \
+     unit_lds_bytes<ELEM_T, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE,                               \
+                    PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>(),                                  \
      &launch_unit<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>, \
      kernel_entry<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>()},
 #define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \

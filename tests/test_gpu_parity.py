@@ -226,3 +226,46 @@ def test_unaligned_pointers_use_plain_kernel(dtype):
         binding.fft_destroy(plan)
     y = buf_out[off:off + n * batch * 2].cpu().numpy().reshape(batch, n, 2)
     assert mismatches(y, oracle.emulate(x, "dual_select", dtype)) == 0
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("logn", list(range(7, 16)))
+def test_pipelined_configurations_over_many_blocks(dtype, logn):
+    """Every pipelined (persistent, two register sets) configuration over a
+    batch of several blocks per resident workgroup, so that both register sets
+    and the prefetch of a next block run, with a ragged last block; sampled
+    transforms (first, last, and random ones) against the oracle."""
+    torch = pytest.importorskip("torch")
+    n = 1 << logn
+    single, _, _ = binding.fft_config_count(n, dtype)
+    elem = 4 if dtype == "f16" else 8
+    batch = (1 << 27) // (n * elem) - 3
+    pipelined = []
+    for v in range(single):
+        p = binding.Plan(n, batch, dtype, "dual_select", variant=(v, 0, False))
+        try:
+            if "pipe=1" in p.info()["config"]:
+                pipelined.append((v, p.info()["config"]))
+        finally:
+            p.close()
+    if not pipelined:
+        pytest.skip("no pipelined configuration at this size")
+    x0 = inputs.uniform(n, 64, 23, dtype)
+    ref0 = oracle.emulate(x0, "dual_select", dtype)
+    xt = torch.from_numpy(x0).to("cuda:0").repeat((batch + 63) // 64, 1, 1)[:batch].contiguous()
+    pick = np.concatenate([[0, 1, batch // 2, batch - 2, batch - 1],
+                           np.random.default_rng(logn).choice(batch, 11, replace=False)])
+    for v, cfg in pipelined:
+        yt = torch.full_like(xt, float("nan"))
+        p = binding.Plan(n, batch, dtype, "dual_select", variant=(v, 0, False))
+        try:
+            p.execute(xt, yt)
+            torch.cuda.synchronize()
+        finally:
+            p.close()
+        y = yt[torch.from_numpy(pick)].cpu().numpy()
+        print(f"pipelined n={n} {dtype} batch={batch} variant={v} {cfg}", flush=True)
+        assert mismatches(y, ref0[pick % 64]) == 0, (v, cfg)
+        del yt
+    del xt
+    torch.cuda.empty_cache()

@@ -13,6 +13,8 @@ import re
 import numpy as np
 import pytest
 
+from paper_2604_00567_amd import binding
+
 CONFIGS = os.path.join(os.path.dirname(os.path.dirname(__file__)),
                        "paper_2604_00567_amd", "csrc", "configs.inc")
 MODES = {"MODE_SMALL": 0, "MODE_COLS": 1, "MODE_ROWS": 2}
@@ -484,3 +486,96 @@ def test_every_column_and_row_config_index_math(cfg):
     assert np.all(w2 == 1)
     ref = np.fft.fft(x.reshape(1, n), axis=1).ravel()
     assert np.max(np.abs(out - ref)) < 1e-9 * n
+
+
+def load_full_configs():
+    """(mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc) of
+    every entry, in registry order."""
+    out = []
+    for line in open(CONFIGS):
+        m = re.match(r"\s*CFG(U|E)?\((\w+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),\s*(\d+),"
+                     r"\s*(\d+),\s*(\d+),\s*(\d+)(?:,\s*(\d+))?(?:,\s*(ENC_\w+))?\)", line)
+        if m:
+            upl = int(m.group(12)) if m.group(1) else 1
+            enc = m.group(13) or "ENC_TABLE"
+            out.append((MODES[m.group(2)],) + tuple(int(m.group(i)) for i in range(3, 12)) + (upl, enc))
+    return out
+
+
+def lds_twiddle_entries(pp, log_nu, log_e, mode, lane):
+    """Entries [L0, L0 R) of the middle pass that a PIPE = 3 workgroup copies
+    into LDS; none where that pass's column is wave-uniform (scalar loads)."""
+    if mode != 0 or lane or pp.np != 3:
+        return 0
+    G = (1 << log_nu) >> log_e
+    if pp.log_m(1) >= 6 and G % 64 == 0:
+        return 0
+    return (1 << (pp.log_l0(1) + pp.lr(1))) - (1 << pp.log_l0(1))
+
+
+def lds_bytes(c, esize, twsize):
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    ex = lds_elems(pp, mode, upw, log_e, esize) * esize
+    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane) if pipe == 3 else 0
+    return ex if te == 0 else (ex + 15) // 16 * 16 + te * twsize
+
+
+def compiled(c, dtype):
+    """The registry's rule (cfg_fits) for an entry and a plan precision."""
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
+    esize, twsize = (4, 8) if dtype == "f16" else (8, 16)
+    if dtype == "f16f32" and (stg or pipe == 1):
+        return False
+    if enc != "ENC_TABLE" and (dtype != "f16" or pipe == 1 or lane):
+        return False
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    if pipe == 3 and lds_twiddle_entries(pp, log_nu, log_e, mode, lane) == 0:
+        return False
+    return lds_bytes(c, esize, twsize) <= LDS_BYTES
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32", "f16f32"])
+def test_compiled_configurations_match_the_model(dtype):
+    """The library's count of whole-transform configurations per size is the
+    count of entries the LDS model and the precision rules admit."""
+    cfgs = [c for c in load_full_configs() if c[0] == 0]
+    for m in range(1, 17):
+        want = sum(1 for c in cfgs if c[1] == m and compiled(c, dtype))
+        assert binding.fft_config_count(1 << m, dtype)[0] == want, (m, dtype)
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] == 3])
+@pytest.mark.parametrize("esize,twsize", [(4, 8), (8, 16)])
+def test_lds_twiddle_copy(cfg, esize, twsize):
+    """PIPE = 3: the copy of the middle pass's entries fills whole 16-byte
+    chunks from a 16-byte aligned table offset, every chunk exactly once,
+    after the exchange area; every lane's pass-1 read lands on the entry the
+    table path reads (q + L0 c), inside the copy."""
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane)
+    assert mode == 0 and te > 0, "a PIPE = 3 entry needs a middle pass to serve"
+    if lds_bytes(cfg, esize, twsize) > LDS_BYTES:
+        pytest.skip("not compiled for this element size")
+    ex = lds_elems(pp, mode, upw, log_e, esize) * esize
+    off = (ex + 15) // 16 * 16
+    L0 = 1 << pp.log_l0(1)
+    R = 1 << pp.lr(1)
+    assert (te * twsize) % 16 == 0 and (L0 * twsize) % 16 == 0 and off >= ex
+    assert off + te * twsize <= LDS_BYTES
+    G = (1 << log_nu) >> log_e
+    nt = (upw // upl) * G
+    chunks = te * twsize // 16
+    seen = sorted(i for t in range(nt) for i in range(t, chunks, nt))
+    assert seen == list(range(chunks))
+    LOGM = pp.log_m(1)
+    GPL = (1 << log_e) // R
+    for t in range(nt):
+        g = t % G
+        for u in range(GPL):
+            q = (g + G * u) >> LOGM
+            assert 0 <= q < L0
+            for c in range(1, R):
+                idx = q + L0 * (c - 1)
+                assert 0 <= idx < te and L0 + idx == q + L0 * c
