@@ -293,21 +293,33 @@ constexpr size_t unit_lds_elems() {
     return exchange_rounds<E, LOG_E, MODE, UPW, PP>() == 2 ? (size_t)PP::half_region()
                                                            : (size_t)UPW * PP::region();
 }
-// Twiddles of the middle pass held in LDS (configurations with PIPE = 3).
-// In a whole-transform unit of three register passes, pass 1 (span L0 before
-// it, radix R) takes for group column q < L0 the entries q + L0 c of the
-// level-ordered table, 1 <= c < R: together the contiguous entries
-// [L0, L0 R).  The workgroup copies them into LDS once, after the exchange
-// area, and pass 1 reads them there instead of through the vector memory
-// path (its lanes read the same L0 (R - 1) entries over and over).  Passes
-// whose column is the same across a wave load through the scalar cache
-// instead (group_twiddles), and take no LDS copy.
+// Twiddles held in LDS (configurations with PIPE = 3).  In a unit whose table
+// offsets are its own (whole transforms and column units: q0 = 0, no level
+// shift), pass P >= 1 (span L0 before it, radix R) takes for group column
+// q < L0 the entries q + L0 c of the level-ordered table, 1 <= c < R: the
+// contiguous entries [L0, L0 R), and passes 1 .. P together take [L0_1,
+// L0_P R_P).  The workgroup copies that run into LDS once, after the exchange
+// area, and the passes read it there instead of through the vector memory
+// path, where many lanes would fetch the same entries: the middle pass of a
+// three-pass whole transform (all lanes of a column), and every pass after
+// the first of a column unit (its lanes run the same groups of UPW columns).
+// A whole transform's last pass reads distinct entries per lane (NU/2 of
+// them) and keeps its table loads; a middle pass whose column is the same
+// across a wave loads through the scalar cache (group_twiddles) instead.
 template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP>
-constexpr int lds_twiddle_entries() {
-    if (MODE != MODE_SMALL || LANE || PP::NP != 3) return 0;
+constexpr int lds_twiddle_last_pass() {
+    if (LANE) return 0;
+    if (MODE == MODE_COLS) return PP::NP >= 2 ? PP::NP - 1 : 0;
+    if (MODE != MODE_SMALL || PP::NP != 3) return 0;
     constexpr int G = (1 << LOG_NU) >> LOG_E;
     if (PP::log_m(1) >= 6 && G % 64 == 0) return 0;
-    return (1 << (PP::log_l0(1) + PP::lr(1))) - (1 << PP::log_l0(1));
+    return 1;
+}
+template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP>
+constexpr int lds_twiddle_entries() {
+    constexpr int LAST = lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP>();
+    if (LAST == 0) return 0;
+    return (1 << (PP::log_l0(LAST) + PP::lr(LAST))) - (1 << PP::log_l0(1));
 }
 // Byte offset of the twiddle copy: the exchange area rounded up to 16 bytes.
 template <class E, int LOG_E, int MODE, int UPW, class PP>
@@ -323,7 +335,7 @@ constexpr size_t unit_lds_bytes() {
 }
 // Whether a configuration fits a workgroup's LDS for element type E (the
 // configuration list serves both element sizes; entries that do not fit are
-// neither compiled nor offered).  PIPE = 3 also needs a middle pass to serve.
+// neither compiled nor offered).  PIPE = 3 also needs a pass to serve.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr bool unit_fits() {
     if (PIPE == 3 && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() == 0) return false;
@@ -704,8 +716,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
-        constexpr bool TWL = Geo::kTwiddleLds && P == 1 &&
-                             lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() > 0;
+        constexpr bool TWL = Geo::kTwiddleLds && P >= 1 &&
+                             P <= lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP>();
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
             TW tw[R];
@@ -713,12 +725,13 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = twp[u * R + c];
             } else if constexpr (TWL) {
-                // entry q + L0 c of the table sits at q + L0 (c - 1) of the copy
+                // entry q + L0 c of the table sits at q + L0 c - L0_1 of the copy
+                constexpr int L01 = 1 << PP::log_l0(1);
                 const TW* ltw = reinterpret_cast<const TW*>(reinterpret_cast<const unsigned char*>(lds) +
                                                             lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>());
                 const int q = (g + G * u) >> LOGM;
 #pragma unroll
-                for (int c = 1; c < R; ++c) tw[c] = ltw[q + L0 * (c - 1)];
+                for (int c = 1; c < R; ++c) tw[c] = ltw[q + L0 * c - L01];
             } else {
                 group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
             }
@@ -905,7 +918,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
     static_assert(PIPE != 2 || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
-    static_assert(PIPE != 3 || MODE == MODE_SMALL, "LDS twiddles need whole-transform units");
+    static_assert(PIPE != 3 || MODE != MODE_ROWS, "LDS twiddles need units with their own table offsets");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
@@ -946,9 +959,10 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
         }
     } else {
         if constexpr (PIPE == 3) {
-            // copy table entries [L0, L0 R) of the middle pass into LDS after
-            // the exchange area, 16 bytes per lane per step; the barrier after
-            // the first exchange's writes orders it before pass 1 reads it
+            // copy the table run of the passes served from LDS (from L0 of
+            // pass 1 on) after the exchange area, 16 bytes per lane per step;
+            // the barrier after the first exchange's writes orders it before
+            // pass 1 reads it
             using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
             using TW = typename TwOf<E>::type;
             constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PPT>();

@@ -502,15 +502,28 @@ def load_full_configs():
     return out
 
 
-def lds_twiddle_entries(pp, log_nu, log_e, mode, lane):
-    """Entries [L0, L0 R) of the middle pass that a PIPE = 3 workgroup copies
-    into LDS; none where that pass's column is wave-uniform (scalar loads)."""
-    if mode != 0 or lane or pp.np != 3:
+def lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane):
+    """Last pass a PIPE = 3 workgroup serves from LDS (from pass 1 on): the
+    middle pass of a three-pass whole transform unless its column is
+    wave-uniform (scalar loads), every later pass of a column unit; 0: none."""
+    if lane:
+        return 0
+    if mode == 1:
+        return pp.np - 1 if pp.np >= 2 else 0
+    if mode != 0 or pp.np != 3:
         return 0
     G = (1 << log_nu) >> log_e
     if pp.log_m(1) >= 6 and G % 64 == 0:
         return 0
-    return (1 << (pp.log_l0(1) + pp.lr(1))) - (1 << pp.log_l0(1))
+    return 1
+
+
+def lds_twiddle_entries(pp, log_nu, log_e, mode, lane):
+    """Table entries [L0 of pass 1, L0 R of the last served pass) in the copy."""
+    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane)
+    if last == 0:
+        return 0
+    return (1 << (pp.log_l0(last) + pp.lr(last))) - (1 << pp.log_l0(1))
 
 
 def lds_bytes(c, esize, twsize):
@@ -535,14 +548,26 @@ def compiled(c, dtype):
     return lds_bytes(c, esize, twsize) <= LDS_BYTES
 
 
+def two_pass_split(m, dtype):
+    """(column, row) log2 NU of the two-pass schedule for N = 2^m, as the
+    library splits it (columns take the larger half)."""
+    c = (m + 1) // 2
+    return c, m - c
+
+
 @pytest.mark.parametrize("dtype", ["f16", "f32", "f16f32"])
 def test_compiled_configurations_match_the_model(dtype):
-    """The library's count of whole-transform configurations per size is the
-    count of entries the LDS model and the precision rules admit."""
-    cfgs = [c for c in load_full_configs() if c[0] == 0]
-    for m in range(1, 17):
-        want = sum(1 for c in cfgs if c[1] == m and compiled(c, dtype))
-        assert binding.fft_config_count(1 << m, dtype)[0] == want, (m, dtype)
+    """The library's count of configurations per size (whole transforms,
+    columns, rows) is the count of entries the LDS model and the precision
+    rules admit."""
+    full = load_full_configs()
+    for m in range(1, 21):
+        single, cols, rows = binding.fft_config_count(1 << m, dtype)
+        want = sum(1 for c in full if c[0] == 0 and c[1] == m and compiled(c, dtype))
+        assert single == want, (m, dtype)
+        lc, lr = two_pass_split(m, dtype)
+        assert cols == sum(1 for c in full if c[0] == 1 and c[1] == lc and compiled(c, dtype)), (m, dtype)
+        assert rows == sum(1 for c in full if c[0] == 2 and c[1] == lr and compiled(c, dtype)), (m, dtype)
 
 
 @pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] == 3])
@@ -555,27 +580,30 @@ def test_lds_twiddle_copy(cfg, esize, twsize):
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane)
-    assert mode == 0 and te > 0, "a PIPE = 3 entry needs a middle pass to serve"
+    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane)
+    assert mode in (0, 1) and te > 0, "a PIPE = 3 entry needs a pass to serve"
     if lds_bytes(cfg, esize, twsize) > LDS_BYTES:
         pytest.skip("not compiled for this element size")
     ex = lds_elems(pp, mode, upw, log_e, esize) * esize
     off = (ex + 15) // 16 * 16
-    L0 = 1 << pp.log_l0(1)
-    R = 1 << pp.lr(1)
-    assert (te * twsize) % 16 == 0 and (L0 * twsize) % 16 == 0 and off >= ex
+    L01 = 1 << pp.log_l0(1)
+    assert (te * twsize) % 16 == 0 and (L01 * twsize) % 16 == 0 and off >= ex
     assert off + te * twsize <= LDS_BYTES
     G = (1 << log_nu) >> log_e
     nt = (upw // upl) * G
     chunks = te * twsize // 16
     seen = sorted(i for t in range(nt) for i in range(t, chunks, nt))
     assert seen == list(range(chunks))
-    LOGM = pp.log_m(1)
-    GPL = (1 << log_e) // R
-    for t in range(nt):
-        g = t % G
-        for u in range(GPL):
-            q = (g + G * u) >> LOGM
-            assert 0 <= q < L0
-            for c in range(1, R):
-                idx = q + L0 * (c - 1)
-                assert 0 <= idx < te and L0 + idx == q + L0 * c
+    for p in range(1, last + 1):
+        L0 = 1 << pp.log_l0(p)
+        R = 1 << pp.lr(p)
+        LOGM = pp.log_m(p)
+        GPL = (1 << log_e) // R
+        for t in range(nt):
+            g = t // upw if mode == 1 else t % G      # column units: unit-fast lanes
+            for u in range(GPL):
+                q = (g + G * u) >> LOGM
+                assert 0 <= q < L0
+                for c in range(1, R):
+                    idx = q + L0 * c - L01
+                    assert 0 <= idx < te and L01 + idx == q + L0 * c
