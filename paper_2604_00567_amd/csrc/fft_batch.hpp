@@ -41,7 +41,7 @@ struct BatchGeo {
     // no twiddle prefetch: the kernel's registers are the largest over all its
     // configurations, and prefetching raises that maximum into spills
     static constexpr bool kTwiddlePrefetch = false;
-    static constexpr bool kTwiddleLds = false;
+    static constexpr int kTwiddleLds = 0;
     static constexpr int kEncoding = ENC_TABLE;
     const int64_t* offs;
     BatchItem it;
@@ -144,7 +144,7 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
 // with unit u of the launch at element offset offs[u].
 struct ListGeo {
     static constexpr bool kTwiddlePrefetch = false;
-    static constexpr bool kTwiddleLds = false;
+    static constexpr int kTwiddleLds = 0;
     static constexpr int kEncoding = ENC_TABLE;
     const int64_t* offs;
     int64_t ublk, units;

@@ -304,20 +304,23 @@ constexpr size_t unit_lds_elems() {
 // three-pass whole transform (all lanes of a column), and every pass after
 // the first of a column unit (its lanes run the same groups of UPW columns).
 // A whole transform's last pass reads distinct entries per lane (NU/2 of
-// them) and keeps its table loads; a middle pass whose column is the same
-// across a wave loads through the scalar cache (group_twiddles) instead.
-template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP>
+// them) and keeps its table loads under PIPE = 3; PIPE = 4 copies those too
+// (every pass after the first reads LDS: the run [L0_1, NU), for transforms
+// small enough that it fits beside the exchange).  Under PIPE = 3 a middle
+// pass whose column is the same across a wave loads through the scalar cache
+// (group_twiddles) instead.
+template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP, int PIPE>
 constexpr int lds_twiddle_last_pass() {
-    if (LANE) return 0;
-    if (MODE == MODE_COLS) return PP::NP >= 2 ? PP::NP - 1 : 0;
+    if (LANE || (PIPE != 3 && PIPE != 4)) return 0;
+    if (MODE == MODE_COLS || (MODE == MODE_SMALL && PIPE == 4)) return PP::NP >= 2 ? PP::NP - 1 : 0;
     if (MODE != MODE_SMALL || PP::NP != 3) return 0;
     constexpr int G = (1 << LOG_NU) >> LOG_E;
     if (PP::log_m(1) >= 6 && G % 64 == 0) return 0;
     return 1;
 }
-template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP>
+template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP, int PIPE>
 constexpr int lds_twiddle_entries() {
-    constexpr int LAST = lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP>();
+    constexpr int LAST = lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>();
     if (LAST == 0) return 0;
     return (1 << (PP::log_l0(LAST) + PP::lr(LAST))) - (1 << PP::log_l0(1));
 }
@@ -326,19 +329,20 @@ template <class E, int LOG_E, int MODE, int UPW, class PP>
 constexpr size_t lds_twiddle_offset() {
     return (unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) + 15) / 16 * 16;
 }
-// LDS bytes of a workgroup: the exchange area, and with PIPE = 3 the twiddle copy.
+// LDS bytes of a workgroup: the exchange area, and with PIPE = 3 or 4 the twiddle copy.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr size_t unit_lds_bytes() {
-    constexpr int TE = PIPE == 3 ? lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() : 0;
+    constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>();
     if (TE == 0) return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E);
     return lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>() + (size_t)TE * sizeof(typename TwOf<E>::type);
 }
 // Whether a configuration fits a workgroup's LDS for element type E (the
 // configuration list serves both element sizes; entries that do not fit are
-// neither compiled nor offered).  PIPE = 3 also needs a pass to serve.
+// neither compiled nor offered).  PIPE = 3 and 4 also need a pass to serve.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr bool unit_fits() {
-    if (PIPE == 3 && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP>() == 0) return false;
+    if ((PIPE == 3 || PIPE == 4) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0)
+        return false;
     return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP>() <= kLdsBytes;
 }
 
@@ -483,12 +487,13 @@ __device__ __forceinline__ void lane_tail(E* v, const typename TwOf<E>::type* __
 // Where the units of one workgroup live: a regular launch takes UPW
 // consecutive units per workgroup (GridGeo); the uneven-batch kernel takes the
 // units of one work item (BatchGeo, in fft_batch.hpp).
-template <bool TWPF, int ENC = ENC_TABLE, bool TWL = false>
+template <bool TWPF, int ENC = ENC_TABLE, int TWL = 0>
 struct GridGeoT {
     // the next pass's twiddles are loaded a pass ahead (twiddle_prefetch)
     static constexpr bool kTwiddlePrefetch = TWPF;
-    // the middle pass reads its twiddles from an LDS copy (lds_twiddle_entries)
-    static constexpr bool kTwiddleLds = TWL;
+    // passes read their twiddles from an LDS copy: 0 none, else the PIPE
+    // value that decides which (lds_twiddle_last_pass)
+    static constexpr int kTwiddleLds = TWL;
     // the butterfly's path encoding (bfly_enc)
     static constexpr int kEncoding = ENC;
     int64_t ublk, units;
@@ -716,8 +721,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
-        constexpr bool TWL = Geo::kTwiddleLds && P >= 1 &&
-                             P <= lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP>();
+        constexpr bool TWL =
+            P >= 1 && P <= lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP, Geo::kTwiddleLds>();
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
             TW tw[R];
@@ -918,7 +923,8 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
     static_assert(PIPE != 2 || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
-    static_assert(PIPE != 3 || MODE != MODE_ROWS, "LDS twiddles need units with their own table offsets");
+    static_assert((PIPE != 3 && PIPE != 4) || MODE != MODE_ROWS,
+                  "LDS twiddles need units with their own table offsets");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
@@ -958,14 +964,14 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             blk += step;
         }
     } else {
-        if constexpr (PIPE == 3) {
+        if constexpr (PIPE == 3 || PIPE == 4) {
             // copy the table run of the passes served from LDS (from L0 of
             // pass 1 on) after the exchange area, 16 bytes per lane per step;
             // the barrier after the first exchange's writes orders it before
             // pass 1 reads it
             using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
             using TW = typename TwOf<E>::type;
-            constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PPT>();
+            constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PPT, PIPE>();
             constexpr int CHUNKS = (int)(TE * sizeof(TW) / 16);
             constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
             static_assert(TE > 0 && (TE * sizeof(TW)) % 16 == 0 && ((1 << LR0) * sizeof(TW)) % 16 == 0,
@@ -974,8 +980,8 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             uint4* dst = reinterpret_cast<uint4*>(lds_raw + lds_twiddle_offset<E, LOG_E, MODE, UPW, PPT>());
             for (int i = (int)threadIdx.x; i < CHUNKS; i += NT) dst[i] = src[i];
         }
-        const GridGeoT<PIPE == 2, ENC, PIPE == 3> gp{(int64_t)blockIdx.x * UPW, units, log_m,
-                                                     (int)threadIdx.x};
+        constexpr int TWL = (PIPE == 3 || PIPE == 4) ? PIPE : 0;
+        const GridGeoT<PIPE == 2, ENC, TWL> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

@@ -502,13 +502,14 @@ def load_full_configs():
     return out
 
 
-def lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane):
+def lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe=3):
     """Last pass a PIPE = 3 workgroup serves from LDS (from pass 1 on): the
     middle pass of a three-pass whole transform unless its column is
-    wave-uniform (scalar loads), every later pass of a column unit; 0: none."""
-    if lane:
+    wave-uniform (scalar loads), every later pass of a column unit; PIPE = 4:
+    every pass after the first of a whole transform; 0: none."""
+    if lane or pipe not in (3, 4):
         return 0
-    if mode == 1:
+    if mode == 1 or (mode == 0 and pipe == 4):
         return pp.np - 1 if pp.np >= 2 else 0
     if mode != 0 or pp.np != 3:
         return 0
@@ -518,9 +519,9 @@ def lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane):
     return 1
 
 
-def lds_twiddle_entries(pp, log_nu, log_e, mode, lane):
+def lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe=3):
     """Table entries [L0 of pass 1, L0 R of the last served pass) in the copy."""
-    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane)
+    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe)
     if last == 0:
         return 0
     return (1 << (pp.log_l0(last) + pp.lr(last))) - (1 << pp.log_l0(1))
@@ -530,7 +531,7 @@ def lds_bytes(c, esize, twsize):
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     ex = lds_elems(pp, mode, upw, log_e, esize) * esize
-    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane) if pipe == 3 else 0
+    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe)
     return ex if te == 0 else (ex + 15) // 16 * 16 + te * twsize
 
 
@@ -543,7 +544,7 @@ def compiled(c, dtype):
     if enc != "ENC_TABLE" and (dtype != "f16" or pipe == 1 or lane):
         return False
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
-    if pipe == 3 and lds_twiddle_entries(pp, log_nu, log_e, mode, lane) == 0:
+    if pipe in (3, 4) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0:
         return False
     return lds_bytes(c, esize, twsize) <= LDS_BYTES
 
@@ -570,18 +571,18 @@ def test_compiled_configurations_match_the_model(dtype):
         assert rows == sum(1 for c in full if c[0] == 2 and c[1] == lr and compiled(c, dtype)), (m, dtype)
 
 
-@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] == 3])
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] in (3, 4)])
 @pytest.mark.parametrize("esize,twsize", [(4, 8), (8, 16)])
 def test_lds_twiddle_copy(cfg, esize, twsize):
-    """PIPE = 3: the copy of the middle pass's entries fills whole 16-byte
+    """PIPE = 3 and 4: the copy of the served passes' entries fills whole 16-byte
     chunks from a 16-byte aligned table offset, every chunk exactly once,
-    after the exchange area; every lane's pass-1 read lands on the entry the
-    table path reads (q + L0 c), inside the copy."""
+    after the exchange area; every lane's read in each served pass lands on
+    the entry the table path reads (q + L0 c), inside the copy."""
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
-    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane)
-    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane)
-    assert mode in (0, 1) and te > 0, "a PIPE = 3 entry needs a pass to serve"
+    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe)
+    last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe)
+    assert mode in (0, 1) and te > 0, "a PIPE = 3 or 4 entry needs a pass to serve"
     if lds_bytes(cfg, esize, twsize) > LDS_BYTES:
         pytest.skip("not compiled for this element size")
     ex = lds_elems(pp, mode, upw, log_e, esize) * esize
