@@ -311,7 +311,7 @@ constexpr size_t unit_lds_elems() {
 // (group_twiddles) instead.
 template <int LOG_NU, int LOG_E, int MODE, int LANE, class PP, int PIPE>
 constexpr int lds_twiddle_last_pass() {
-    if (LANE || (PIPE != 3 && PIPE != 4)) return 0;
+    if (LANE || (PIPE != 3 && PIPE != 4 && PIPE != 5)) return 0;
     if (MODE == MODE_COLS || (MODE == MODE_SMALL && PIPE == 4)) return PP::NP >= 2 ? PP::NP - 1 : 0;
     if (MODE != MODE_SMALL || PP::NP != 3) return 0;
     constexpr int G = (1 << LOG_NU) >> LOG_E;
@@ -329,7 +329,7 @@ template <class E, int LOG_E, int MODE, int UPW, class PP>
 constexpr size_t lds_twiddle_offset() {
     return (unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) + 15) / 16 * 16;
 }
-// LDS bytes of a workgroup: the exchange area, and with PIPE = 3 or 4 the twiddle copy.
+// LDS bytes of a workgroup: the exchange area, and with PIPE = 3, 4 or 5 the twiddle copy.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr size_t unit_lds_bytes() {
     constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>();
@@ -338,10 +338,10 @@ constexpr size_t unit_lds_bytes() {
 }
 // Whether a configuration fits a workgroup's LDS for element type E (the
 // configuration list serves both element sizes; entries that do not fit are
-// neither compiled nor offered).  PIPE = 3 and 4 also need a pass to serve.
+// neither compiled nor offered).  PIPE = 3, 4 and 5 also need a pass to serve.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr bool unit_fits() {
-    if ((PIPE == 3 || PIPE == 4) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0)
+    if ((PIPE == 3 || PIPE == 4 || PIPE == 5) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0)
         return false;
     return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP>() <= kLdsBytes;
 }
@@ -671,11 +671,17 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 
         // ---- the next pass's twiddles (whole-transform units), issued ahead of
         // this pass's gather; the empty asm keeps them ahead of it
+        // (passes served from an LDS copy of the table neither prefetch nor
+        // take prefetched twiddles)
         constexpr bool PF = Geo::kTwiddlePrefetch && !PRE &&
                             twiddle_prefetch<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE>();
-        constexpr int NEXT_TW = (PF && P + 1 < NP) ? (EL >> PP::lr(P + 1)) << PP::lr(P + 1) : 1;
+        constexpr int TWL_LAST = lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP, Geo::kTwiddleLds>();
+        constexpr bool TWL = P >= 1 && P <= TWL_LAST;
+        constexpr bool PFN = PF && P + 1 < NP && !(P + 1 <= TWL_LAST);   // prefetch pass P + 1's
+        constexpr bool PFU = PF && P > 0 && !TWL;                         // use this pass's prefetch
+        constexpr int NEXT_TW = PFN ? (EL >> PP::lr(P + 1)) << PP::lr(P + 1) : 1;
         TW twn[NEXT_TW];
-        if constexpr (PF && P + 1 < NP) {
+        if constexpr (PFN) {
             pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P + 1>(twn, lt, geo0, g);
             asm volatile("" ::: "memory");
         }
@@ -721,12 +727,10 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         }
 
         // ---- twiddles (once per group position) and stages (for each unit)
-        constexpr bool TWL =
-            P >= 1 && P <= lds_twiddle_last_pass<LOG_NU, LOG_E, MODE, LANE, PP, Geo::kTwiddleLds>();
 #pragma unroll
         for (int u = 0; u < GPL; ++u) {
             TW tw[R];
-            if constexpr (PF && P > 0) {
+            if constexpr (PFU) {
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = twp[u * R + c];
             } else if constexpr (TWL) {
@@ -743,7 +747,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
             for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding>(v + k * EL + u * R, tw);
         }
-        if constexpr (PF && P + 1 < NP) {
+        if constexpr (PFN) {
             // entries c >= 1 of each group are the loaded ones
 #pragma unroll
             for (int i = 0; i < NEXT_TW; ++i)
@@ -922,8 +926,8 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
-    static_assert(PIPE != 2 || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
-    static_assert((PIPE != 3 && PIPE != 4) || MODE != MODE_ROWS,
+    static_assert((PIPE != 2 && PIPE != 5) || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
+    static_assert((PIPE != 3 && PIPE != 4 && PIPE != 5) || MODE != MODE_ROWS,
                   "LDS twiddles need units with their own table offsets");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
@@ -964,7 +968,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             blk += step;
         }
     } else {
-        if constexpr (PIPE == 3 || PIPE == 4) {
+        if constexpr (PIPE == 3 || PIPE == 4 || PIPE == 5) {
             // copy the table run of the passes served from LDS (from L0 of
             // pass 1 on) after the exchange area, 16 bytes per lane per step;
             // the barrier after the first exchange's writes orders it before
@@ -980,8 +984,11 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             uint4* dst = reinterpret_cast<uint4*>(lds_raw + lds_twiddle_offset<E, LOG_E, MODE, UPW, PPT>());
             for (int i = (int)threadIdx.x; i < CHUNKS; i += NT) dst[i] = src[i];
         }
-        constexpr int TWL = (PIPE == 3 || PIPE == 4) ? PIPE : 0;
-        const GridGeoT<PIPE == 2, ENC, TWL> gp{(int64_t)blockIdx.x * UPW, units, log_m, (int)threadIdx.x};
+        // PIPE = 5: the middle pass from LDS (as PIPE = 3) and the last pass's
+        // twiddles prefetched a pass ahead (as PIPE = 2)
+        constexpr int TWL = (PIPE == 3 || PIPE == 4 || PIPE == 5) ? PIPE : 0;
+        const GridGeoT<PIPE == 2 || PIPE == 5, ENC, TWL> gp{(int64_t)blockIdx.x * UPW, units, log_m,
+                                                             (int)threadIdx.x};
         unit_pass<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, 0, 0>(v, lds, lt, in, out,
                                                                                gp);
     }

@@ -506,8 +506,9 @@ def lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe=3):
     """Last pass a PIPE = 3 workgroup serves from LDS (from pass 1 on): the
     middle pass of a three-pass whole transform unless its column is
     wave-uniform (scalar loads), every later pass of a column unit; PIPE = 4:
-    every pass after the first of a whole transform; 0: none."""
-    if lane or pipe not in (3, 4):
+    every pass after the first of a whole transform; PIPE = 5 as PIPE = 3
+    (its prefetch serves the other passes); 0: none."""
+    if lane or pipe not in (3, 4, 5):
         return 0
     if mode == 1 or (mode == 0 and pipe == 4):
         return pp.np - 1 if pp.np >= 2 else 0
@@ -544,7 +545,7 @@ def compiled(c, dtype):
     if enc != "ENC_TABLE" and (dtype != "f16" or pipe == 1 or lane):
         return False
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
-    if pipe in (3, 4) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0:
+    if pipe in (3, 4, 5) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0:
         return False
     return lds_bytes(c, esize, twsize) <= LDS_BYTES
 
@@ -571,10 +572,10 @@ def test_compiled_configurations_match_the_model(dtype):
         assert rows == sum(1 for c in full if c[0] == 2 and c[1] == lr and compiled(c, dtype)), (m, dtype)
 
 
-@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] in (3, 4)])
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] in (3, 4, 5)])
 @pytest.mark.parametrize("esize,twsize", [(4, 8), (8, 16)])
 def test_lds_twiddle_copy(cfg, esize, twsize):
-    """PIPE = 3 and 4: the copy of the served passes' entries fills whole 16-byte
+    """PIPE = 3, 4 and 5: the copy of the served passes' entries fills whole 16-byte
     chunks from a 16-byte aligned table offset, every chunk exactly once,
     after the exchange area; every lane's read in each served pass lands on
     the entry the table path reads (q + L0 c), inside the copy."""
@@ -582,7 +583,7 @@ def test_lds_twiddle_copy(cfg, esize, twsize):
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe)
     last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe)
-    assert mode in (0, 1) and te > 0, "a PIPE = 3 or 4 entry needs a pass to serve"
+    assert mode in (0, 1) and te > 0, "a PIPE = 3, 4 or 5 entry needs a pass to serve"
     if lds_bytes(cfg, esize, twsize) > LDS_BYTES:
         pytest.skip("not compiled for this element size")
     ex = lds_elems(pp, mode, upw, log_e, esize) * esize
