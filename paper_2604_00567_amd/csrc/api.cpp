@@ -57,7 +57,7 @@ int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<Devi
         *out = it->second;
         return FFT_OK;
     }
-    const int64_t ncap = std::max<int64_t>(n, 4096);
+    const int64_t ncap = std::max<int64_t>(n, kMinTableEntries);
     std::vector<uint8_t> img = build_level_table(ncap, dtype, kind, inverse);
     auto t = std::make_shared<DeviceTable>();
     t->ncap = ncap;

@@ -18,11 +18,28 @@
 
 #include "batch_launch.hpp"
 #include "fft_device.hpp"
+#include "tables.hpp"
 
 namespace dsfft {
 
 constexpr int kBatchThreads = kHostBatchThreads;
 constexpr int kBatchMaxElems = 32;     // elements per lane, largest configuration
+// Table entries [0, T) sit in LDS below the exchange area, copied once per
+// workgroup of the persistent kernel: every pass after the first whose
+// entries lie below T (binary16, T = 1024: all of them up to 2^10 points,
+// the middle passes beyond, the column items' second pass; binary32, whose
+// exchange leaves less room, T = 512) reads its twiddles there instead of
+// through the vector memory path, where the lanes of a workgroup fetched the
+// same entries again and again.
+template <class E>
+constexpr int batch_twiddle_prefix() {
+    return sizeof(E) == 4 ? 1024 : 512;
+}
+static_assert(batch_twiddle_prefix<uint32_t>() <= kMinTableEntries, "the prefix lies inside every device table");
+template <class E>
+constexpr size_t batch_prefix_bytes() {
+    return (size_t)batch_twiddle_prefix<E>() * sizeof(typename TwOf<E>::type);
+}
 
 // Work item (layout in batch_launch.hpp):
 //   cfg        configuration id (HostBatchCfg), one compiled unit configuration
@@ -36,12 +53,14 @@ constexpr int kBatchMaxElems = 32;     // elements per lane, largest configurati
 //   out_off    column items: transform start in the workspace; row items: in the output
 using BatchItem = HostBatchItem;
 
-// Unit geometry of one work item.
+// Unit geometry of one work item (TPX: the LDS table prefix).
+template <int TPX>
 struct BatchGeo {
     // no twiddle prefetch: the kernel's registers are the largest over all its
     // configurations, and prefetching raises that maximum into spills
     static constexpr bool kTwiddlePrefetch = false;
     static constexpr int kTwiddleLds = 0;
+    static constexpr int kTwiddlePrefix = TPX;
     static constexpr int kEncoding = ENC_TABLE;
     const int64_t* offs;
     BatchItem it;
@@ -76,16 +95,16 @@ struct BatchGeo {
     __device__ __forceinline__ int64_t block_units(int) const { return 0; }
 };
 
-template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2>
+template <class E, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, class Geo>
 __device__ __forceinline__ void batch_unit(E* lds, const typename TwOf<E>::type* __restrict__ lt,
-                                           const E* src, E* dst, const BatchGeo& geo) {
+                                           const E* src, E* dst, const Geo& geo) {
     static_assert((UPW << (LOG_NU - LOG_E)) == kBatchThreads, "batch configurations use 512 threads");
     static_assert((1 << LOG_E) <= kBatchMaxElems, "too many elements per lane");
     E v[1 << LOG_E];   // per configuration, so each case keeps its own registers
     // The thread index is read through an empty asm statement in each case:
     // index arithmetic common to several cases then cannot be hoisted above
     // the dispatch, where it would stay live in every case.
-    BatchGeo g = geo;
+    Geo g = geo;
     g.lane_id = (int)threadIdx.x;
     asm volatile("" : "+v"(g.lane_id));
     unit_pass<E, LOG_NU, LOG_E, UPW, 1, MODE, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, src, dst, g);
@@ -109,10 +128,10 @@ constexpr int batch_lds_elems() {
     return m;
 }
 
-template <class E>
+template <class E, class Geo>
 __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
                                                const typename TwOf<E>::type* __restrict__ lt,
-                                               const E* in, E* out, E* ws, const BatchGeo& g) {
+                                               const E* in, E* out, E* ws, const Geo& g) {
     switch (cfg) {
         case HB_N2: batch_unit<E, 1, 1, 512, MODE_SMALL, 1, 0, 0>(lds, lt, in, out, g); break;
         case HB_N4: batch_unit<E, 2, 2, 512, MODE_SMALL, 2, 0, 0>(lds, lt, in, out, g); break;
@@ -141,10 +160,13 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
 
 // Whole transforms too large for the batch kernel's LDS (binary16, 2^15 and
 // 2^16 points) run in a kernel of their own, one transform per workgroup,
-// with unit u of the launch at element offset offs[u].
+// with unit u of the launch at element offset offs[u]; table entries [0, TPX)
+// sit in LDS below the exchange area (the middle pass reads them there).
+template <int TPX>
 struct ListGeo {
     static constexpr bool kTwiddlePrefetch = false;
     static constexpr int kTwiddleLds = 0;
+    static constexpr int kTwiddlePrefix = TPX;
     static constexpr int kEncoding = ENC_TABLE;
     const int64_t* offs;
     int64_t ublk, units;
@@ -164,14 +186,18 @@ struct ListGeo {
     __device__ __forceinline__ int64_t block_units(int) const { return 0; }
 };
 
-template <class E, int LOG_NU, int LOG_E, int LR0, int LR1, int LR2>
+template <class E, int LOG_NU, int LOG_E, int LR0, int LR1, int LR2, int TPX>
 __global__ void __launch_bounds__(1 << (LOG_NU - LOG_E))
 fft_list_kernel(const E* in, E* out, const typename TwOf<E>::type* __restrict__ lt,
                 const int64_t* __restrict__ offs, int64_t count) {
+    using TW = typename TwOf<E>::type;
+    static_assert(TPX <= kMinTableEntries, "the prefix lies inside every device table");
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-    E* lds = reinterpret_cast<E*>(lds_raw);
+    // the first exchange's barrier orders the copy before the middle pass
+    copy_table_prefix<TW, TPX, (1 << (LOG_NU - LOG_E))>(lt, lds_raw);
+    E* lds = reinterpret_cast<E*>(lds_raw + (size_t)TPX * sizeof(TW));
     E v[1 << LOG_E];
-    const ListGeo gp{offs, (int64_t)blockIdx.x, count, (int)threadIdx.x};
+    const ListGeo<TPX> gp{offs, (int64_t)blockIdx.x, count, (int)threadIdx.x};
     unit_pass<E, LOG_NU, LOG_E, 1, 1, MODE_SMALL, LR0, LR1, LR2, 0, 0, 0, 0>(v, lds, lt, in, out, gp);
 }
 
@@ -186,7 +212,9 @@ fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __res
                  int first, int nitems, unsigned* q) {
     unsigned* head = q;
     extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
-    E* lds = reinterpret_cast<E*>(lds_raw);
+    // the barrier after the first claim publishes the copy
+    copy_table_prefix<typename TwOf<E>::type, batch_twiddle_prefix<E>(), kBatchThreads>(lt, lds_raw);
+    E* lds = reinterpret_cast<E*>(lds_raw + batch_prefix_bytes<E>());
     // Claims run one item ahead: the claim of the next item is issued when
     // the current one starts, so its round trip overlaps the current item's
     // work, and published in LDS when the item ends.  Two slots alternate:
@@ -203,7 +231,7 @@ fft_batch_kernel(const E* in, E* out, E* ws, const typename TwOf<E>::type* __res
         // the returned index is needed only at the end of the item
         const unsigned next = threadIdx.x == 0 ? atomicAdd(head, 1u) : 0u;
         const BatchItem it = items[first + idx];
-        const BatchGeo geo{offs, it, 0};
+        const BatchGeo<batch_twiddle_prefix<E>()> geo{offs, it, 0};
         // An opaque copy of the table pointer per item keeps each case's
         // twiddle address arithmetic inside the loop; hoisted out of it, the
         // addresses of every case would stay live across the whole loop.

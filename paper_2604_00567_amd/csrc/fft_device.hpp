@@ -494,6 +494,8 @@ struct GridGeoT {
     // passes read their twiddles from an LDS copy: 0 none, else the PIPE
     // value that decides which (lds_twiddle_last_pass)
     static constexpr int kTwiddleLds = TWL;
+    // leading table entries held in LDS just below the exchange area (none)
+    static constexpr int kTwiddlePrefix = 0;
     // the butterfly's path encoding (bfly_enc)
     static constexpr int kEncoding = ENC;
     int64_t ublk, units;
@@ -622,6 +624,18 @@ constexpr bool twiddle_prefetch() {
     return true;
 }
 
+// Copies table entries [0, T) into LDS at dst (16-byte aligned), 16 bytes per
+// lane per step, for NT lanes; the caller's next barrier publishes them.
+template <class TW, int T, int NT>
+__device__ __forceinline__ void copy_table_prefix(const TW* __restrict__ lt, unsigned char* dst) {
+    constexpr int CHUNKS = (int)(T * sizeof(TW) / 16);
+    static_assert((T * sizeof(TW)) % 16 == 0, "whole 16-byte chunks");
+    const uint4* src = reinterpret_cast<const uint4*>(lt);
+    uint4* d = reinterpret_cast<uint4*>(dst);
+#pragma unroll
+    for (int i = (int)threadIdx.x; i < CHUNKS; i += NT) d[i] = src[i];
+}
+
 // Marks a prefetched twiddle as needed here: the loads that fill it must have
 // returned by this point (and the compiler cannot move them after it).
 __device__ __forceinline__ void pin_twiddle(TwH& t) { asm volatile("" : "+v"(t.w), "+v"(t.ts)); }
@@ -679,6 +693,11 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr bool TWL = P >= 1 && P <= TWL_LAST;
         constexpr bool PFN = PF && P + 1 < NP && !(P + 1 <= TWL_LAST);   // prefetch pass P + 1's
         constexpr bool PFU = PF && P > 0 && !TWL;                         // use this pass's prefetch
+        // table entries [0, TPX) held in LDS just below the exchange area
+        // (persistent and list kernels): a pass P >= 1 of a unit with its own
+        // table offsets whose entries q + L0 c all lie below TPX reads them there
+        constexpr int TPX = Geo::kTwiddlePrefix;
+        constexpr bool TWX = !TWL && !PFU && TPX > 0 && P >= 1 && MODE != MODE_ROWS && (L0 << LR) <= TPX;
         constexpr int NEXT_TW = PFN ? (EL >> PP::lr(P + 1)) << PP::lr(P + 1) : 1;
         TW twn[NEXT_TW];
         if constexpr (PFN) {
@@ -741,6 +760,12 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 const int q = (g + G * u) >> LOGM;
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = ltw[q + L0 * c - L01];
+            } else if constexpr (TWX) {
+                const TW* ltp = reinterpret_cast<const TW*>(reinterpret_cast<const unsigned char*>(lds) -
+                                                            (size_t)TPX * sizeof(TW));
+                const int q = (g + G * u) >> LOGM;
+#pragma unroll
+                for (int c = 1; c < R; ++c) tw[c] = ltp[q + L0 * c];
             } else {
                 group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
             }

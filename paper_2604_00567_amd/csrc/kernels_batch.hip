@@ -6,8 +6,12 @@ namespace dsfft {
 
 template <class E>
 static size_t batch_lds_bytes_t() {
-    return (size_t)batch_lds_elems() * sizeof(E);
+    return batch_prefix_bytes<E>() + (size_t)batch_lds_elems() * sizeof(E);
 }
+
+static_assert(batch_prefix_bytes<uint32_t>() + (size_t)batch_lds_elems() * sizeof(uint32_t) <= kLdsBytes &&
+                  batch_prefix_bytes<f2_t>() + (size_t)batch_lds_elems() * sizeof(f2_t) <= kLdsBytes,
+              "the persistent kernel fits a workgroup's LDS");
 
 size_t batch_lds_bytes(int dtype) {
     return dtype == 0 ? batch_lds_bytes_t<uint32_t>() : batch_lds_bytes_t<f2_t>();
@@ -19,17 +23,25 @@ const void* batch_kernel_func(int dtype) {
 
 // The binary16 list kernels, 1024 threads each: 2^16 points with 64 elements
 // per lane (radix 2^6, 2^5, 2^5; each exchange in two rounds of half the rows)
-// and 2^15 points with 32 (radix 2^5 passes).
-#define DSFFT_LIST16 fft_list_kernel<uint32_t, 16, 6, 6, 5, 5>
-#define DSFFT_LIST15 fft_list_kernel<uint32_t, 15, 5, 5, 5, 5>
+// and 2^15 points with 32 (radix 2^5 passes); the middle pass reads table
+// entries [L0, L0 R) from the LDS prefix (2048 and 1024 entries).
+#define DSFFT_LIST16 fft_list_kernel<uint32_t, 16, 6, 6, 5, 5, 2048>
+#define DSFFT_LIST15 fft_list_kernel<uint32_t, 15, 5, 5, 5, 5, 1024>
 static_assert(kListLog[0] == 16 && kListLog[1] == 15 && kListThreads == (1 << (16 - 6)) &&
                   kListThreads == (1 << (15 - 5)),
               "list kernel geometry");
 
 size_t batch_list_lds_bytes(int list) {
-    return list == 0 ? unit_lds_elems<uint32_t, 6, MODE_SMALL, 1, PassPlan<16, 6, 5, 5, 0>>() * sizeof(uint32_t)
-                     : unit_lds_elems<uint32_t, 5, MODE_SMALL, 1, PassPlan<15, 5, 5, 5, 0>>() * sizeof(uint32_t);
+    return list == 0 ? 2048 * sizeof(TwH) +
+                           unit_lds_elems<uint32_t, 6, MODE_SMALL, 1, PassPlan<16, 6, 5, 5, 0>>() * sizeof(uint32_t)
+                     : 1024 * sizeof(TwH) +
+                           unit_lds_elems<uint32_t, 5, MODE_SMALL, 1, PassPlan<15, 5, 5, 5, 0>>() * sizeof(uint32_t);
 }
+static_assert(2048 * sizeof(TwH) + unit_lds_elems<uint32_t, 6, MODE_SMALL, 1, PassPlan<16, 6, 5, 5, 0>>() *
+                                       sizeof(uint32_t) <= kLdsBytes &&
+                  1024 * sizeof(TwH) + unit_lds_elems<uint32_t, 5, MODE_SMALL, 1, PassPlan<15, 5, 5, 5, 0>>() *
+                                           sizeof(uint32_t) <= kLdsBytes,
+              "list kernels fit a workgroup's LDS");
 
 const void* batch_list_func(int list) {
     return list == 0 ? (const void*)&DSFFT_LIST16 : (const void*)&DSFFT_LIST15;

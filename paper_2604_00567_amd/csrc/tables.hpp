@@ -26,6 +26,9 @@ size_t entry_bytes(int dtype);
 
 // Device image with entry L/2 + j = T_L[j] for L = 2 .. ncap (entry 0 unused);
 // `inverse`: the tables of the inverse transform (conjugate twiddles).
+// Device tables are built for ncap >= kMinTableEntries, so kernels may copy
+// that many leading entries whatever sizes their plan or batch holds.
+constexpr int64_t kMinTableEntries = 4096;
 std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind, bool inverse);
 
 // Flat table T_n[k], k < n/2: rounded mult and ratio (binary16 bits or float)
