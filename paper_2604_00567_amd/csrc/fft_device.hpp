@@ -324,6 +324,13 @@ constexpr int lds_twiddle_entries() {
     if (LAST == 0) return 0;
     return (1 << (PP::log_l0(LAST) + PP::lr(LAST))) - (1 << PP::log_l0(1));
 }
+// Row units (PIPE = 3): the first pass of row q0 takes entries
+// q0 + c 2^log_m, 1 <= c < R0, the same for the G lanes of the unit; the
+// workgroup copies entry (c, unit) to LDS slot (c - 1) UPW + unit.
+template <int MODE, int UPW, class PP, int PIPE>
+constexpr int lds_row_twiddle_entries() {
+    return (MODE == MODE_ROWS && PIPE == 3) ? ((1 << PP::lr(0)) - 1) * UPW : 0;
+}
 // Byte offset of the twiddle copy: the exchange area rounded up to 16 bytes.
 template <class E, int LOG_E, int MODE, int UPW, class PP>
 constexpr size_t lds_twiddle_offset() {
@@ -332,7 +339,8 @@ constexpr size_t lds_twiddle_offset() {
 // LDS bytes of a workgroup: the exchange area, and with PIPE = 3, 4 or 5 the twiddle copy.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr size_t unit_lds_bytes() {
-    constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>();
+    constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() +
+                       lds_row_twiddle_entries<MODE, UPW, PP, PIPE>();
     if (TE == 0) return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E);
     return lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>() + (size_t)TE * sizeof(typename TwOf<E>::type);
 }
@@ -341,7 +349,8 @@ constexpr size_t unit_lds_bytes() {
 // neither compiled nor offered).  PIPE = 3, 4 and 5 also need a pass to serve.
 template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
 constexpr bool unit_fits() {
-    if ((PIPE == 3 || PIPE == 4 || PIPE == 5) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0)
+    if ((PIPE == 3 || PIPE == 4 || PIPE == 5) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0 &&
+        lds_row_twiddle_entries<MODE, UPW, PP, PIPE>() == 0)
         return false;
     return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP>() <= kLdsBytes;
 }
@@ -760,6 +769,11 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
                 const int q = (g + G * u) >> LOGM;
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = ltw[q + L0 * c - L01];
+            } else if constexpr (P == 0 && MODE == MODE_ROWS && Geo::kTwiddleLds == 3) {
+                const TW* ltw = reinterpret_cast<const TW*>(reinterpret_cast<const unsigned char*>(lds) +
+                                                            lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>());
+#pragma unroll
+                for (int c = 1; c < R; ++c) tw[c] = ltw[(c - 1) * UPW + ul0];
             } else if constexpr (TWX) {
                 const TW* ltp = reinterpret_cast<const TW*>(reinterpret_cast<const unsigned char*>(lds) -
                                                             (size_t)TPX * sizeof(TW));
@@ -952,8 +966,8 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     E* lds = reinterpret_cast<E*>(lds_raw);
     static_assert(PIPE != 1 || (STG == 0 && MODE == MODE_SMALL), "pipelining needs unstaged units");
     static_assert((PIPE != 2 && PIPE != 5) || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
-    static_assert((PIPE != 3 && PIPE != 4 && PIPE != 5) || MODE != MODE_ROWS,
-                  "LDS twiddles need units with their own table offsets");
+    static_assert((PIPE != 4 && PIPE != 5) || MODE != MODE_ROWS,
+                  "LDS twiddles of later passes need units with their own table offsets");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
@@ -993,7 +1007,23 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             blk += step;
         }
     } else {
-        if constexpr (PIPE == 3 || PIPE == 4 || PIPE == 5) {
+        if constexpr (PIPE == 3 && MODE == MODE_ROWS) {
+            // row units: entry (c, unit) of the first pass, one 8- or 16-byte
+            // entry per lane per step; the first pass reads them right after
+            // its loads, so a barrier publishes them
+            using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
+            using TW = typename TwOf<E>::type;
+            constexpr int TE = lds_row_twiddle_entries<MODE, UPW, PPT, PIPE>();
+            constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
+            TW* dst = reinterpret_cast<TW*>(lds_raw + lds_twiddle_offset<E, LOG_E, MODE, UPW, PPT>());
+            const int64_t ublk = (int64_t)blockIdx.x * UPW;
+            for (int i = (int)threadIdx.x; i < TE; i += NT) {
+                const int c = 1 + i / UPW, ul = i % UPW;
+                const UnitGeom geo = unit_geom<LOG_NU, MODE>(ublk + ul, log_m);   // q0 < 2^log_m
+                dst[i] = lt[geo.q0 + ((int64_t)c << geo.log_lb)];
+            }
+            __syncthreads();
+        } else if constexpr (PIPE == 3 || PIPE == 4 || PIPE == 5) {
             // copy the table run of the passes served from LDS (from L0 of
             // pass 1 on) after the exchange area, 16 bytes per lane per step;
             // the barrier after the first exchange's writes orders it before

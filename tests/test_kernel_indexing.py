@@ -528,11 +528,17 @@ def lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe=3):
     return (1 << (pp.log_l0(last) + pp.lr(last))) - (1 << pp.log_l0(1))
 
 
+def lds_row_twiddle_entries(c):
+    """Row units, PIPE = 3: entry (c, unit) of the first pass per workgroup."""
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
+    return ((1 << lr0) - 1) * upw if (mode == 2 and pipe == 3) else 0
+
+
 def lds_bytes(c, esize, twsize):
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     ex = lds_elems(pp, mode, upw, log_e, esize) * esize
-    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe)
+    te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) + lds_row_twiddle_entries(c)
     return ex if te == 0 else (ex + 15) // 16 * 16 + te * twsize
 
 
@@ -545,7 +551,8 @@ def compiled(c, dtype):
     if enc != "ENC_TABLE" and (dtype != "f16" or pipe == 1 or lane):
         return False
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
-    if pipe in (3, 4, 5) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0:
+    if pipe in (3, 4, 5) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0 \
+            and lds_row_twiddle_entries(c) == 0:
         return False
     return lds_bytes(c, esize, twsize) <= LDS_BYTES
 
@@ -572,7 +579,41 @@ def test_compiled_configurations_match_the_model(dtype):
         assert rows == sum(1 for c in full if c[0] == 2 and c[1] == lr and compiled(c, dtype)), (m, dtype)
 
 
-@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] in (3, 4, 5)])
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] == 3 and c[0] == 2])
+@pytest.mark.parametrize("esize,twsize", [(4, 8), (8, 16)])
+def test_lds_row_twiddle_copy(cfg, esize, twsize):
+    """Row units, PIPE = 3: the copy loop writes slot (c - 1) UPW + unit once
+    for every first-pass entry c of every unit, after the exchange area, and
+    each lane of unit ul reads slot (c - 1) UPW + ul, the entry q0 + c 2^log_m
+    of its own row."""
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    if lds_bytes(cfg, esize, twsize) > LDS_BYTES:
+        pytest.skip("not compiled for this element size")
+    te = lds_row_twiddle_entries(cfg)
+    R0 = 1 << lr0
+    G = (1 << log_nu) >> log_e
+    nt = upw * G
+    for log_m in (6, 9):
+        ublk = 3 * upw
+        slots = {}
+        for t in range(nt):
+            for i in range(t, te, nt):
+                c, ul = 1 + i // upw, i % upw
+                q0 = (ublk + ul) & ((1 << log_m) - 1)
+                assert i not in slots
+                slots[i] = q0 + (c << log_m)
+        assert sorted(slots) == list(range(te))
+        for t in range(nt):
+            ul = t // G
+            q0 = (ublk + ul) & ((1 << log_m) - 1)
+            for c in range(1, R0):
+                assert slots[(c - 1) * upw + ul] == q0 + (c << log_m)
+    ex = lds_elems(pp, mode, upw, log_e, esize) * esize
+    assert (ex + 15) // 16 * 16 + te * twsize <= LDS_BYTES
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[9] in (3, 4, 5) and c[0] != 2])
 @pytest.mark.parametrize("esize,twsize", [(4, 8), (8, 16)])
 def test_lds_twiddle_copy(cfg, esize, twsize):
     """PIPE = 3, 4 and 5: the copy of the served passes' entries fills whole 16-byte
