@@ -135,7 +135,21 @@ int fft_table_build_dir(int64_t n, fft_dtype dtype, fft_table_kind kind, int dir
                         void* mult_out, void* ratio_out, uint8_t* path_out);
 
 /* The plan's parameters and its kernel choice, for tests and reports.
- * config_out receives a NUL-terminated description (up to `cap` bytes). */
+ * config_out receives a NUL-terminated description (up to `cap` bytes):
+ * "mode:nu=2^a,e=2^b,upw=U,r=[r0,r1,r2],stg=S,lane=L,pipe=P,t=T,lds=B"
+ * (mode small / cols / rows; a unit of 2^a points, 2^b elements per lane, U
+ * units per workgroup, register passes of radix 2^r0, 2^r1, 2^r2; S = 1:
+ * 16-byte LDS-staged I/O; L = 1: last two stages across lanes; T threads and
+ * B bytes of LDS per workgroup), then ",upl=K" when a lane holds K units,
+ * ",enc=select" / ",enc=branch" for the path-encoding variants, and for a
+ * two-pass plan " | rows:... | chunk=C" (its second kernel, and the
+ * transforms per workspace chunk).  P says where
+ * twiddles come from besides per-lane table loads: 1 persistent workgroups
+ * with a second register set, 2 the next pass's twiddles loaded a pass
+ * ahead, 3 an LDS copy for the passes many lanes share (a whole transform's
+ * middle pass, a column unit's later passes, a row unit's first pass), 4 an
+ * LDS copy for every pass after the first, 5 as 3 plus 2 for the last pass.
+ * All variants produce bit-identical results. */
 int fft_plan_info(const fft_plan* plan, int64_t* n, int64_t* batch, int* dtype, int* kind,
                   char* config_out, size_t cap);
 
