@@ -270,3 +270,34 @@ def test_pipelined_configurations_over_many_blocks(dtype, logn):
         del yt
     del xt
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("n,dtype", [(1 << 17, "f16"), (1 << 20, "f16"), (1 << 16, "f32"),
+                                     (1 << 20, "f32")])
+def test_large_n_sweep_full_size_sampled(n, dtype):
+    """Large-N sweep at its full size (batch * N = 2^26 elements, tone inputs)
+    through the library's default (tuned) two-pass plan: a block of distinct
+    transforms tiled over the batch on the device, sampled transforms (the
+    first two, the last, and the two on either side of the middle, which is a
+    boundary between 128 MiB workspace chunks at every size here) bit for bit
+    against the oracle."""
+    torch = pytest.importorskip("torch")
+    batch = (1 << 26) // n
+    distinct = 4
+    x0 = inputs.tones(n, distinct, 19, dtype)
+    xt = torch.from_numpy(x0).to("cuda:0").repeat(batch // distinct, 1, 1).contiguous()
+    yt = torch.empty_like(xt)
+    plan = binding.Plan(n, batch, dtype, "dual_select")
+    try:
+        cfg = plan.info()["config"]
+        plan.execute(xt, yt)
+        torch.cuda.synchronize()
+    finally:
+        plan.close()
+    print(f"large-N sweep n={n} {dtype} batch={batch} {cfg}", flush=True)
+    assert " | " in cfg                                   # the two-pass schedule
+    ref = oracle.emulate(x0, "dual_select", dtype)
+    for b in sorted({0, 1, batch // 2 - 1, batch // 2, batch - 1}):
+        assert mismatches(yt[b].cpu().numpy()[None], ref[b % distinct][None]) == 0, b
+    del xt, yt
+    torch.cuda.empty_cache()
