@@ -20,11 +20,33 @@ def test_tune_records_fastest_bit_exact(n, dtype, tmp_path):
     choice = binding.fft_tuned_choice(n, dtype)
     assert choice is not None and list(choice) == [best["variant"][0], best["variant"][1],
                                                    bool(best["variant"][2])]
-    p = binding.Plan(n, 4, dtype, "dual_select")
+    p = binding.Plan(n, max(1, (1 << 22) // n), dtype, "dual_select")
     try:
         assert p.info()["config"].split(" | ")[0] == best["config"].split(" | ")[0]
     finally:
         p.close()
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32", "f16f32"])
+def test_small_batch_takes_one_transform_per_workgroup(dtype):
+    """A batch too small to give every compute unit a workgroup under the
+    tuned configuration runs one transform per workgroup (where the size has
+    such a configuration), with the same results bit for bit."""
+    import oracle
+    from paper_2604_00567_amd import inputs
+    from tests.gpu_util import mismatches, run_gpu
+    n = 1024
+    small = binding.Plan(n, 16, dtype, "dual_select")
+    large = binding.Plan(n, 1 << 16, dtype, "dual_select")
+    try:
+        assert ",upw=1," in small.info()["config"] and "pipe=0" in small.info()["config"]
+        assert ",upw=1," not in large.info()["config"]
+    finally:
+        small.close()
+        large.close()
+    x = inputs.normal(n, 16, 1, "f16" if dtype != "f32" else "f32")
+    ref = oracle.emulate(x, "dual_select", dtype)
+    assert mismatches(run_gpu(x, dtype, "dual_select"), ref) == 0
 
 
 def test_batch_tune_returns_choices():
