@@ -169,8 +169,11 @@ float orc_fma32(float a, float b, float c) { return fmaf(a, b, c); }
 /* precision of the emulation */
 enum { PREC_F16 = 16, PREC_F32 = 32, PREC_F64 = 64 };
 
+static inline double round_p(int prec, double x);
+
 static inline double fma_p(int prec, double a, double b, double c) {
     if (ORC_MUTANT == 5 && prec == PREC_F16) return fma(a, b, c);
+    if (ORC_MUTANT == 6 && prec != PREC_F64) return round_p(prec, round_p(prec, a * b) + c);
     if (prec == PREC_F16) return orc_fma16(a, b, c);
     if (prec == PREC_F32) return (double)fmaf((float)a, (float)b, (float)c);
     return fma(a, b, c);

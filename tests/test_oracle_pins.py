@@ -2,7 +2,8 @@
 
 Each test checks the oracle against something other than itself: values the
 paper prints (tests/golden/paper_facts.txt), a hand-worked FP16 example
-(tests/golden/fp16_n4_worked.txt), closed forms, Parseval, linearity, the DFT
+(tests/golden/fp16_n4_worked.txt) and two N = 8 examples whose products are
+inexact (tests/golden/fp16_n8_inexact.txt, fp32_n8_inexact.txt), closed forms, Parseval, linearity, the DFT
 written out, numpy's FFT, numpy's binary16 cast and exact rational rounding.
 """
 import math
@@ -284,6 +285,19 @@ def test_fp16_hand_worked_n4():
     assert np.array_equal(y, rows[:, 3:5])
 
 
+@pytest.mark.parametrize("fname,dtype,npdt", [("fp16_n8_inexact.txt", "f16", np.float16),
+                                              ("fp32_n8_inexact.txt", "f32", np.float32)])
+def test_hand_worked_n8_inexact_products(fname, dtype, npdt):
+    # the W^1 and W^3 entries have m = RN(cos(pi/4)), so every s*m of the last
+    # pass is inexact and each of those eight results depends on the FMA being
+    # rounded once (Sec. II-B/II-C)
+    rows = np.loadtxt(os.path.join(GOLDEN, fname))
+    x = rows[:, 1:3].astype(npdt)[None]
+    assert np.array_equal(x.astype(np.float64)[0], rows[:, 1:3])     # inputs exact
+    y = oracle.emulate(x, "dual_select", dtype)[0].astype(np.float64)
+    assert np.array_equal(y, rows[:, 3:5])
+
+
 def test_fp16_exact_for_small_integers_n4():
     # at N = 4 every dual-select twiddle is exactly 1 or -j in binary16, so small
     # integer inputs transform exactly
@@ -343,12 +357,16 @@ def _pin_checks():
             assert rel(cplx(oracle.emulate(x, kind, "f64")), cplx(oracle.dft64(x))) < 1e-13
     def worked_check():
         test_fp16_hand_worked_n4()
+    def worked_inexact_f16():
+        test_hand_worked_n8_inexact_products("fp16_n8_inexact.txt", "f16", np.float16)
+    def worked_inexact_f32():
+        test_hand_worked_n8_inexact_products("fp32_n8_inexact.txt", "f32", np.float32)
     def bound_check():
         test_fp16_within_cumulative_bound_and_realistic()
-    return [dft_check, worked_check, bound_check]
+    return [dft_check, worked_check, worked_inexact_f16, worked_inexact_f32, bound_check]
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
 def test_planted_mistakes_are_caught(mutant, tmp_path):
     import ctypes
     import subprocess
