@@ -283,10 +283,14 @@ class Server:
 
 
 def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", seed: int = 0,
-                    budget_bytes: int = 64 << 30) -> dict:
+                    budget_bytes: int = 64 << 30, keep_io: dict = None) -> dict:
     """Same trace, one launch per request (cached regular plans), round-robin
     over `streams` streams, admitted in arrival order under the same HBM
-    budget as the continuous loop (request bytes in flight)."""
+    budget as the continuous loop (request bytes in flight).
+
+    Plans are cached per (shape, stream): a two-pass plan owns one workspace
+    and must not run on two streams at once, so each stream has its own.
+    ``keep_io``: a dict that receives {rid: (input, output)} device copies."""
     gen = torch.Generator(device="cuda")
     gen.manual_seed(seed)
     sts = [torch.cuda.Stream() for _ in range(streams)]
@@ -308,15 +312,20 @@ def run_per_request(trace: dict, streams: int = 4, kind: str = "dual_select", se
         while nxt < total and t_arr[nxt] <= now and (
                 inflight_bytes + nb[nxt] <= budget_bytes or not inflight):
             n, b, dt = int(trace["n"][nxt]), int(trace["batch"][nxt]), str(trace["dtype"][nxt])
-            key = (n, b, dt)
+            si = k % streams
+            k += 1
+            st = sts[si]
+            key = (n, b, dt, si)
             if key not in plans:
                 plans[key] = binding.Plan(n, b, dt, kind)
-            st = sts[k % streams]
-            k += 1
             with torch.cuda.stream(st):
                 buf = torch.empty((b, n, 2), dtype=TORCH_DTYPE[dt], device="cuda")
                 buf.normal_(0.0, 1.0, generator=gen)
+                if keep_io is not None:
+                    x_in = buf.clone()
                 plans[key].execute(buf, buf, stream=st)
+                if keep_io is not None:
+                    keep_io[nxt] = (x_in, buf)
                 ev = torch.cuda.Event()
                 ev.record(st)
             inflight[nxt] = (ev, buf)

@@ -51,7 +51,10 @@ def check_all(sizes, x, y, dtype):
 
 @pytest.mark.parametrize("dtype", ["f16", "f32"])
 def test_every_size_in_one_launch(dtype):
-    sizes = np.array([1 << m for m in range(1, 17)] * 3 + [1024] * 20 + [64] * 40, dtype=np.int64)
+    # every size the batch accepts, 2 .. 2^18: whole-transform items, the
+    # binary16 2^15/2^16 list kernels and the column/row split of the larger
+    # sizes (binary16 2^17-2^18, binary32 2^15-2^18)
+    sizes = np.array([1 << m for m in range(1, 19)] * 3 + [1024] * 20 + [64] * 40, dtype=np.int64)
     np.random.default_rng(1).shuffle(sizes)
     x = inputs.packed_uniform(sizes, 41, dtype)
     (y,), info = run_batch(sizes, x, dtype)

@@ -13,9 +13,21 @@ from tests.gpu_util import mismatches
 pytestmark = pytest.mark.gpu
 
 
-def small_trace(k, seed, rate=200000.0, log_hi=14):
-    tr = inputs.poisson_trace(rate, k / rate, seed, log_lo=8, log_hi=log_hi, batch_hi=8)
+def small_trace(k, seed, rate=200000.0, log_hi=14, batch_hi=8):
+    tr = inputs.poisson_trace(rate, k / rate, seed, log_lo=8, log_hi=log_hi, batch_hi=batch_hi)
     return tr
+
+
+def plan_alone(x, n, b, dt):
+    import torch
+    y = torch.empty_like(x)
+    p = binding.Plan(n, b, dt, "dual_select")
+    try:
+        p.execute(x.view(b, n, 2), y.view(b, n, 2))
+        torch.cuda.synchronize()
+    finally:
+        p.close()
+    return y
 
 
 def test_results_alone_equal_results_in_mix():
@@ -105,3 +117,57 @@ def test_per_request_baseline_runs():
     tr = small_trace(200, 23, rate=20000.0)
     stats = run_per_request(tr, streams=2)
     assert stats["requests"] == tr["t"].size and stats["p99_ms"] >= stats["p50_ms"] > 0
+
+
+def test_large_requests_alone_equal_results_in_mix():
+    """The serving workload's full size range (N up to 2^18, batch up to 64):
+    the column/row split of binary16 2^17-2^18 and binary32 2^15-2^18 runs in
+    the slots' batch kernels beside whole transforms; every split-size request
+    and a sample of the others equal a regular plan on the same input, and a
+    few equal the oracle's emulation."""
+    import torch
+    tr = small_trace(160, 31, rate=400000.0, log_hi=18, batch_hi=64)
+    srv = Server(slots=3, slot_bytes=512 << 20, keep_io=True, seed=9)
+    try:
+        stats = srv.run(tr, max_step_requests=32)
+        torch.cuda.synchronize()
+    finally:
+        srv.close()
+    assert stats["requests"] == tr["t"].size
+    assert stats["mean_requests_per_step"] > 1.0
+    n_all, b_all, d_all = tr["n"], tr["batch"], tr["dtype"]
+    split_ids = [r for r in range(tr["t"].size)
+                 if n_all[r] > (1 << (16 if d_all[r] == "f16" else 14))]
+    assert any(d_all[r] == "f16" for r in split_ids) and any(d_all[r] == "f32" for r in split_ids)
+    rng = np.random.default_rng(1)
+    others = [r for r in range(tr["t"].size) if r not in split_ids]
+    check = split_ids[:24] + list(rng.choice(others, 16, replace=False))
+    for rid in check:
+        n, b, dt = int(n_all[rid]), int(b_all[rid]), str(d_all[rid])
+        y_alone = plan_alone(srv.inputs[rid], n, b, dt)
+        assert mismatches(srv.outputs[rid].cpu().numpy(), y_alone.cpu().numpy()) == 0, (rid, n, b, dt)
+    small_split = [r for r in split_ids if n_all[r] * b_all[r] <= (1 << 21)][:3]
+    for rid in small_split + check[-3:]:
+        n, b, dt = int(n_all[rid]), int(b_all[rid]), str(d_all[rid])
+        x = srv.inputs[rid].reshape(b, n, 2).cpu().numpy()
+        y = srv.outputs[rid].reshape(b, n, 2).cpu().numpy()
+        assert mismatches(y, oracle.emulate(x, "dual_select", dt)) == 0, (rid, n, b, dt)
+
+
+def test_per_request_baseline_two_pass_plans_per_stream():
+    """One launch per request with many same-shape two-pass requests in flight
+    on several streams at once: each stream's plan has its own workspace, so
+    every result equals the same plan run alone."""
+    import torch
+    k = 48
+    tr = {"t": np.linspace(0.0, 1e-4, k), "n": np.full(k, 1 << 17, np.int64),
+          "batch": np.full(k, 4, np.int64),
+          "dtype": np.array(["f16", "f32"] * (k // 2))}
+    io = {}
+    stats = run_per_request(tr, streams=4, seed=3, keep_io=io)
+    torch.cuda.synchronize()
+    assert stats["requests"] == k and len(io) == k
+    for rid, (x, y) in io.items():
+        n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+        y_alone = plan_alone(x, n, b, dt)
+        assert mismatches(y.cpu().numpy(), y_alone.cpu().numpy()) == 0, (rid, dt)
