@@ -18,6 +18,9 @@ gcc into ``oracle/_liboracle.so``:
   (lf-s)-(lf-B), each FMA rounded once to the working precision (and
   ``emulate(..., "f16f32")``: binary16 data, binary32 butterflies, one rounding
   of each result to binary16);
+* ``emulate4``: the radix-4 form (Sec. VI generality): canonical radix-4
+  Stockham order, 22-FMA butterflies whose twiddle multiplications each take
+  their own min-ratio entry, every FMA rounded once;
 * ``errors``: relative L2, max-abs (complex modulus) and non-finite count;
 * ``analytic_bounds``: per-butterfly and cumulative bounds of eqs.
   (per-butterfly-error) and (cumulative), as printed in Tables I-II.
@@ -69,12 +72,18 @@ def _load():
         "orc_emulate_f64": [i64, i64, i32, i32, dp, dp],
         "orc_emulate_f32": [i64, i64, i32, i32, dp, dp],
         "orc_emulate_f16": [i64, i64, i32, i32, dp, dp],
+        "orc_emulate4_f64": [i64, i64, i32, i32, dp, dp],
+        "orc_emulate4_f32": [i64, i64, i32, i32, dp, dp],
+        "orc_emulate4_f16": [i64, i64, i32, i32, dp, dp],
+        "orc_table_count": [i64, i32, i32, i64, dp, dp, dp],
+        "orc_pairs4": [i64, i32, i32, dp, dp],
         "orc_rn16_array": [i64, dp, dp],
         "orc_f16_to_double_array": [i64, dp, dp],
     }.items():
         f = getattr(lib, name)
         f.argtypes = args
-        f.restype = ctypes.c_int if name.startswith(("orc_table", "orc_fft", "orc_dft", "orc_emu")) else None
+        f.restype = ctypes.c_int if name.startswith(("orc_table", "orc_fft", "orc_dft", "orc_emu",
+                                                     "orc_pairs")) else None
     lib.orc_fma16.argtypes = [ctypes.c_double] * 3
     lib.orc_fma16.restype = ctypes.c_double
     lib.orc_fma32.argtypes = [ctypes.c_float] * 3
@@ -177,6 +186,56 @@ def emulate(x: np.ndarray, kind="dual_select", prec: str = "f16", inverse: bool 
     if rc != 0:
         raise ValueError("emulation failed")
     return out
+
+
+def emulate4(x: np.ndarray, kind="dual_select", prec: str = "f16", inverse: bool = False) -> np.ndarray:
+    """Radix-4 form of the method (Sec. VI, generality): the canonical radix-4
+    Stockham order (a radix-2 stage of span 2 first when log2 N is odd), each
+    radix-4 butterfly as 22 FMAs whose three twiddle multiplications take
+    their own table entries and whose odd pair takes the larger multiplier
+    with the ratio |rho| <= 1; every FMA rounded once to ``prec``."""
+    lib = _load()
+    inv = int(inverse)
+    if prec == "f16":
+        x = _as_batch(x, np.float16)
+        out = np.empty_like(x)
+        rc = lib.orc_emulate4_f16(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
+    elif prec == "f32":
+        x = _as_batch(x, np.float32)
+        out = np.empty_like(x)
+        rc = lib.orc_emulate4_f32(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
+    elif prec == "f64":
+        x = _as_batch(x, np.float64)
+        out = np.empty_like(x)
+        rc = lib.orc_emulate4_f64(x.shape[1], x.shape[0], _kind(kind), inv, _ptr(x), _ptr(out))
+    else:
+        raise ValueError(prec)
+    if rc != 0:
+        raise ValueError("radix-4 emulation failed")
+    return out
+
+
+def table_count(n: int, count: int, kind="dual_select", inverse: bool = False):
+    """FP64 table entries of W^k for k < count (the radix-4 form uses
+    count = 3n/4): (mult, ratio, path)."""
+    lib = _load()
+    mult = np.empty(count, np.float64)
+    ratio = np.empty(count, np.float64)
+    path = np.empty(count, np.int32)
+    if lib.orc_table_count(n, _kind(kind), int(inverse), count, _ptr(mult), _ptr(ratio), _ptr(path)) != 0:
+        raise ValueError(f"bad table request n={n} count={count}")
+    return mult, ratio, path
+
+
+def pairs4(n: int, kind="dual_select", inverse: bool = False):
+    """Odd-pair choice of the radix-4 butterflies of span n, j < n/4:
+    (rho, sel) with sel = 1 where W^j's multiplier is the outer one."""
+    lib = _load()
+    rho = np.empty(n // 4, np.float64)
+    sel = np.empty(n // 4, np.int32)
+    if lib.orc_pairs4(n, _kind(kind), int(inverse), _ptr(rho), _ptr(sel)) != 0:
+        raise ValueError(f"bad pair request n={n}")
+    return rho, sel
 
 
 def rn16(x: np.ndarray) -> np.ndarray:

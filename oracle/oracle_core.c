@@ -85,29 +85,32 @@ double orc_theta(int64_t k, int64_t n) {
  *       others are Linzer-Feig.
  * Returns 0, or -1 on a bad argument.
  */
+static void table_entry(int64_t k, int64_t n, int kind, int inverse, double* mult, double* ratio,
+                        int32_t* path) {
+    double th = orc_theta(k, n);
+    double wr = cos(th), wi = sin(th);
+    if (inverse) wi = -wi;                  /* W^{-k}: the conjugate */
+    int use_cos;
+    if (kind == K_DUAL_SELECT) use_cos = fabs(wr) >= fabs(wi);
+    else if (kind == K_COSINE) use_cos = 1;
+    else if (kind == K_LF_W0_EXEMPT) use_cos = (k == 0);
+    else use_cos = 0;
+    if (use_cos) {
+        *mult = wr;
+        *ratio = wi / wr;
+        *path = P_COS;
+    } else {
+        double d = wi;
+        if (kind == K_LINZER_FEIG && fabs(d) < ORC_EPS_CLAMP) d = ORC_EPS_CLAMP;
+        *mult = d;
+        *ratio = wr / d;
+        *path = P_SIN;
+    }
+}
+
 int orc_table_dir(int64_t n, int kind, int inverse, double* mult, double* ratio, int32_t* path) {
     if (!is_pow2(n) || kind < 0 || kind > 3) return -1;
-    for (int64_t k = 0; k < n / 2; ++k) {
-        double th = orc_theta(k, n);
-        double wr = cos(th), wi = sin(th);
-        if (inverse) wi = -wi;                  /* W^{-k}: the conjugate */
-        int use_cos;
-        if (kind == K_DUAL_SELECT) use_cos = fabs(wr) >= fabs(wi);
-        else if (kind == K_COSINE) use_cos = 1;
-        else if (kind == K_LF_W0_EXEMPT) use_cos = (k == 0);
-        else use_cos = 0;
-        if (use_cos) {
-            mult[k] = wr;
-            ratio[k] = wi / wr;
-            path[k] = P_COS;
-        } else {
-            double d = wi;
-            if (kind == K_LINZER_FEIG && fabs(d) < ORC_EPS_CLAMP) d = ORC_EPS_CLAMP;
-            mult[k] = d;
-            ratio[k] = wr / d;
-            path[k] = P_SIN;
-        }
-    }
+    for (int64_t k = 0; k < n / 2; ++k) table_entry(k, n, kind, inverse, &mult[k], &ratio[k], &path[k]);
     return 0;
 }
 
@@ -320,6 +323,237 @@ int orc_emulate_f16(int64_t n, int64_t batch, int kind, int inverse, const uint1
     if (!a || !b) { free(a); free(b); return -1; }
     for (size_t i = 0; i < cnt; ++i) a[i] = orc_f16_to_double(in[i]);
     int rc = emulate_batch(n, batch, kind, inverse, PREC_F16, a, b);
+    for (size_t i = 0; i < cnt && rc == 0; ++i) out[i] = orc_rn16(b[i]);
+    free(a); free(b);
+    return rc;
+}
+
+/* ------------------------------------------------- radix-4 butterflies */
+
+/*
+ * Radix-4 form of the method (Sec. VI, "Generality": in a radix-r butterfly
+ * every twiddle multiplication picks its own min-ratio factorisation).
+ *
+ * Canonical order for N = 2^m: when m is odd, one radix-2 stage of span 2 (the
+ * six-FMA butterfly with the W^0 entry) comes first; then radix-4 Stockham
+ * DIT stages of span L = 4, 16, ... (m even) or 8, 32, ... (m odd) up to N.
+ * A radix-4 stage of span L holds Y[r][q] at r + (N/L) q and, for r < N/L and
+ * j < L/4, combines the four DFTs of span L/4 at residues r + p N/L:
+ *   a = Y'[r][j], b = Y'[r + N/L][j], c = Y'[r + 2N/L][j], d = Y'[r + 3N/L][j]
+ * (Y'[r'][j] at r' + (4N/L) j) with W1 = W^{jN/L}, W2 = W1^2, W3 = W1^3:
+ *   Y[r][j]          = (a + W2 c) + (W1 b + W3 d)
+ *   Y[r][j + L/4]    = (a - W2 c) - j (W1 b - W3 d)
+ *   Y[r][j + L/2]    = (a + W2 c) - (W1 b + W3 d)
+ *   Y[r][j + 3L/4]   = (a - W2 c) + j (W1 b - W3 d).
+ * Each twiddle W^k (k < 3N/4) has its own table entry (m, t, path) from the
+ * rules of Algorithm 1.  With the sine-path s1 negated, both paths write
+ * W b = m * h, h = (h1, h2):
+ *   cosine: h1 = s1 = b_r - t b_i, h2 = s2 = t b_r + b_i   (eq. (berg-s))
+ *   sine:   h1 = -s1 = -(b_i - t b_r), h2 = s2 = b_r + t b_i (eq. (lf-s))
+ * (two FMAs; negation is exact).  The odd pair W1 b +- W3 d = m1 h_b +- m3 h_d
+ * takes the larger of |m1|, |m3| as its outer multiplier M and the ratio
+ * rho = (smaller m) / (larger m), so |rho| <= 1 as every twiddle ratio:
+ *   |m1| >= |m3|: M = m1, rho = m3/m1, g0 = h_b + rho h_d, g1 = h_b - rho h_d
+ *   otherwise:    M = m3, rho = m1/m3, g0 = rho h_b + h_d, g1 = rho h_b - h_d
+ * so that W1 b + W3 d = M g0 and W1 b - W3 d = M g1.  The butterfly is then
+ *   h_b, h_c, h_d                       6 FMAs
+ *   u0 = a + m2 h_c, u1 = a - m2 h_c    4 FMAs
+ *   g0, g1                              4 FMAs
+ *   Y0 = u0 + M g0, Y2 = u0 - M g0,
+ *   Y1 = u1 - j M g1 = (u1_r + M g1_i, u1_i - M g1_r),
+ *   Y3 = u1 + j M g1 = (u1_r - M g1_i, u1_i + M g1_r)   8 FMAs
+ * 22 FMAs per radix-4 butterfly (two radix-2 stages take 24), each rounded
+ * once.  rho and the choice of M come from the FP64 multipliers and rho is
+ * rounded once to the working precision, like m and t.
+ * The inverse transform (twiddles W^{-k}) turns the rotations -j and +j of
+ * the odd terms into +j and -j: Y1 and Y3 trade places.
+ */
+
+/* Table of the radix-4 form: entries k < count of W^k for size n. */
+int orc_table_count(int64_t n, int kind, int inverse, int64_t count, double* mult, double* ratio,
+                    int32_t* path) {
+    if (!is_pow2(n) || kind < 0 || kind > 3 || count < 0 || count > n) return -1;
+    for (int64_t k = 0; k < count; ++k) table_entry(k, n, kind, inverse, &mult[k], &ratio[k], &path[k]);
+    return 0;
+}
+
+/* Pair choice of the radix-4 butterfly for column j < n/4 of the last stage
+ * (span n): sel = 1 when |m(W^j)| >= |m(W^{3j})| (outer multiplier m1), and
+ * rho, both from the FP64 multipliers. */
+static void pair_choice(double m1, double m3, int* sel, double* rho) {
+    *sel = fabs(m1) >= fabs(m3);
+    *rho = *sel ? m3 / m1 : m1 / m3;
+}
+
+int orc_pairs4(int64_t n, int kind, int inverse, double* rho, int32_t* sel) {
+    if (!is_pow2(n) || n < 4 || kind < 0 || kind > 3) return -1;
+    for (int64_t j = 0; j < n / 4; ++j) {
+        double m1, t1, m3, t3;
+        int32_t p1, p3;
+        int s;
+        table_entry(j, n, kind, inverse, &m1, &t1, &p1);
+        table_entry(3 * j, n, kind, inverse, &m3, &t3, &p3);
+        pair_choice(m1, m3, &s, &rho[j]);
+        sel[j] = s;
+    }
+    return 0;
+}
+
+/* h = (h1, h2) with W b = m h (see above). */
+static inline void scaled4(int prec, int path, double t, double br, double bi, double* h1, double* h2) {
+    if (path == P_COS) {
+        *h1 = fma_p(prec, -t, bi, br);
+        *h2 = fma_p(prec, t, br, bi);
+    } else {
+        *h1 = -fma_p(prec, -t, br, bi);
+        *h2 = fma_p(prec, t, bi, br);
+    }
+}
+
+typedef struct { double m, t; int32_t path; } tw4_t;
+
+static void bfly22(int prec, tw4_t w1, tw4_t w2, tw4_t w3, int sel, double rho,
+                   const double* a, const double* b, const double* c, const double* d,
+                   double* y0, double* y1, double* y2, double* y3) {
+    double hb[2], hc[2], hd[2], u0[2], u1[2], g0[2], g1[2], M;
+    scaled4(prec, w1.path, w1.t, b[0], b[1], &hb[0], &hb[1]);
+    scaled4(prec, w2.path, w2.t, c[0], c[1], &hc[0], &hc[1]);
+    scaled4(prec, w3.path, w3.t, d[0], d[1], &hd[0], &hd[1]);
+    for (int i = 0; i < 2; ++i) {
+        u0[i] = fma_p(prec, w2.m, hc[i], a[i]);
+        u1[i] = fma_p(prec, -w2.m, hc[i], a[i]);
+    }
+    if (sel) {
+        M = w1.m;
+        for (int i = 0; i < 2; ++i) {
+            g0[i] = fma_p(prec, rho, hd[i], hb[i]);
+            g1[i] = fma_p(prec, ORC_MUTANT == 7 ? rho : -rho, hd[i], hb[i]);
+        }
+    } else {
+        M = w3.m;
+        for (int i = 0; i < 2; ++i) {
+            g0[i] = fma_p(prec, rho, hb[i], hd[i]);
+            g1[i] = fma_p(prec, rho, hb[i], -hd[i]);
+        }
+    }
+    y0[0] = fma_p(prec, M, g0[0], u0[0]);
+    y0[1] = fma_p(prec, M, g0[1], u0[1]);
+    y2[0] = fma_p(prec, -M, g0[0], u0[0]);
+    y2[1] = fma_p(prec, -M, g0[1], u0[1]);
+    y1[0] = fma_p(prec, M, g1[1], u1[0]);
+    y1[1] = fma_p(prec, ORC_MUTANT == 8 ? M : -M, g1[0], u1[1]);
+    y3[0] = fma_p(prec, -M, g1[1], u1[0]);
+    y3[1] = fma_p(prec, M, g1[0], u1[1]);
+}
+
+/* Canonical radix-4 order (see above) over the rounded table of W^k,
+ * k < 3n/4 (mult, ratio, path) and the FP64 multipliers m64 for the pair
+ * choice.  y, z: work arrays of 2n doubles; result left in y. */
+static void stockham4_emulate(int64_t n, int prec, int inverse, const double* mult, const double* ratio,
+                              const int32_t* path, const double* m64, double* y, double* z) {
+    int mlog = log2i(n);
+    int64_t L = 4;
+    if (mlog % 2) {
+        /* radix-2 stage of span 2: Y[r][0] = x[r] + x[r + n/2], Y[r][1] = difference */
+        for (int64_t r = 0; r < n / 2; ++r) {
+            double Ar, Ai, Br, Bi;
+            bfly6(prec, path[0], mult[0], ratio[0], y[2 * r], y[2 * r + 1], y[2 * (r + n / 2)],
+                  y[2 * (r + n / 2) + 1], &Ar, &Ai, &Br, &Bi);
+            z[2 * r] = Ar; z[2 * r + 1] = Ai;
+            z[2 * (r + n / 2)] = Br; z[2 * (r + n / 2) + 1] = Bi;
+        }
+        memcpy(y, z, sizeof(double) * 2 * (size_t)n);
+        L = 8;
+    }
+    for (; L <= n; L *= 4) {
+        int64_t nl = n / L, q4 = L / 4;
+        for (int64_t r = 0; r < nl; ++r) {
+            for (int64_t j = 0; j < q4; ++j) {
+                int64_t k1 = j * nl, k2 = 2 * k1, k3 = 3 * k1;
+                tw4_t w1 = {mult[k1], ratio[k1], path[k1]};
+                tw4_t w2 = {mult[k2], ratio[k2], path[k2]};
+                tw4_t w3 = {mult[k3], ratio[k3], path[k3]};
+                int sel;
+                double rho;
+                pair_choice(m64[k1], m64[k3], &sel, &rho);
+                if (ORC_MUTANT != 9) rho = round_p(prec, rho);
+                const double* a = y + 2 * (r + 4 * nl * j);
+                const double* b = y + 2 * (r + nl + 4 * nl * j);
+                const double* c = y + 2 * (r + 2 * nl + 4 * nl * j);
+                const double* d = y + 2 * (r + 3 * nl + 4 * nl * j);
+                int64_t p1 = inverse ? 3 : 1, p3 = inverse ? 1 : 3;
+                bfly22(prec, w1, w2, w3, sel, rho, a, b, c, d, z + 2 * (r + nl * j),
+                       z + 2 * (r + nl * (j + p1 * q4)), z + 2 * (r + nl * (j + 2 * q4)),
+                       z + 2 * (r + nl * (j + p3 * q4)));
+            }
+        }
+        memcpy(y, z, sizeof(double) * 2 * (size_t)n);
+    }
+}
+
+static int emulate4_batch(int64_t n, int64_t batch, int kind, int inverse, int prec,
+                          const double* in, double* out) {
+    if (!is_pow2(n) || batch < 0 || kind < 0 || kind > 3) return -1;
+    int64_t cnt = n < 4 ? 1 : 3 * n / 4;
+    double* mult = (double*)malloc(sizeof(double) * cnt);
+    double* ratio = (double*)malloc(sizeof(double) * cnt);
+    double* m64 = (double*)malloc(sizeof(double) * cnt);
+    int32_t* path = (int32_t*)malloc(sizeof(int32_t) * cnt);
+    if (!mult || !ratio || !m64 || !path) {
+        free(mult); free(ratio); free(m64); free(path);
+        return -1;
+    }
+    orc_table_count(n, kind, inverse, cnt, mult, ratio, path);
+    for (int64_t k = 0; k < cnt; ++k) {
+        m64[k] = mult[k];
+        mult[k] = round_p(prec, mult[k]);
+        ratio[k] = round_p(prec, ratio[k]);
+    }
+    int err = 0;
+#pragma omp parallel
+    {
+        double* y = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+        double* z = (double*)malloc(sizeof(double) * 2 * (size_t)n);
+        if (!y || !z) {
+#pragma omp atomic write
+            err = -1;
+        }
+#pragma omp for schedule(static)
+        for (int64_t b = 0; b < batch; ++b) {
+            if (!y || !z) continue;
+            for (int64_t i = 0; i < 2 * n; ++i) y[i] = round_p(prec, in[b * 2 * n + i]);
+            stockham4_emulate(n, prec, inverse, mult, ratio, path, m64, y, z);
+            memcpy(out + b * 2 * n, y, sizeof(double) * 2 * (size_t)n);
+        }
+        free(y); free(z);
+    }
+    free(mult); free(ratio); free(m64); free(path);
+    return err;
+}
+
+int orc_emulate4_f64(int64_t n, int64_t batch, int kind, int inverse, const double* in, double* out) {
+    return emulate4_batch(n, batch, kind, inverse, PREC_F64, in, out);
+}
+
+int orc_emulate4_f32(int64_t n, int64_t batch, int kind, int inverse, const float* in, float* out) {
+    size_t cnt = (size_t)(2 * n * batch);
+    double* a = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
+    double* b = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
+    if (!a || !b) { free(a); free(b); return -1; }
+    for (size_t i = 0; i < cnt; ++i) a[i] = (double)in[i];
+    int rc = emulate4_batch(n, batch, kind, inverse, PREC_F32, a, b);
+    for (size_t i = 0; i < cnt && rc == 0; ++i) out[i] = (float)b[i];
+    free(a); free(b);
+    return rc;
+}
+
+int orc_emulate4_f16(int64_t n, int64_t batch, int kind, int inverse, const uint16_t* in, uint16_t* out) {
+    size_t cnt = (size_t)(2 * n * batch);
+    double* a = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
+    double* b = (double*)malloc(sizeof(double) * (cnt ? cnt : 1));
+    if (!a || !b) { free(a); free(b); return -1; }
+    for (size_t i = 0; i < cnt; ++i) a[i] = orc_f16_to_double(in[i]);
+    int rc = emulate4_batch(n, batch, kind, inverse, PREC_F16, a, b);
     for (size_t i = 0; i < cnt && rc == 0; ++i) out[i] = orc_rn16(b[i]);
     free(a); free(b);
     return rc;
