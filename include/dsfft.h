@@ -114,6 +114,30 @@ fft_plan* fft_plan_create_dir(int64_t n, int64_t batch, fft_dtype dtype, fft_tab
  */
 int fft_execute(fft_plan* plan, const void* in, void* out, void* stream);
 
+/* Size of the library's fixed device scratch array (64 MiB per GPU). */
+#define FFT_SCRATCH_BYTES ((size_t)64 << 20)
+
+/*
+ * For callers that cannot allocate device memory while they run transforms
+ * (code under HIP graph capture, tight serving loops, hosts that forbid
+ * hipMalloc): fft_execute with no allocation of any kind.  The result is
+ * bit-identical to fft_execute's (same kernels).  A two-pass plan's
+ * intermediate goes through the library's fixed device array of
+ * FFT_SCRATCH_BYTES per GPU, floor(FFT_SCRATCH_BYTES / (n * w)) transforms at
+ * a time (w = 4 bytes for FFT_F16, 8 for FFT_F32 and FFT_F16_F32), instead of
+ * the plan's workspace; single-pass plans use no scratch.  The array is
+ * allocated with the library's code on each GPU and held until the process
+ * ends; its device address is looked up on the first call with a device
+ * current.  Every element of the scratch is written before it is read, so no
+ * clearing is needed.  All calls on one GPU share its array: two calls of
+ * two-pass plans that overlap in time on one GPU (on different streams, or
+ * from different threads) race and give wrong results; calls on one stream
+ * are ordered and safe.  The plan's device must be current.
+ * Returns FFT_OK, FFT_EINVAL (as fft_execute; also a plan of another device,
+ * or one transform whose intermediate exceeds FFT_SCRATCH_BYTES) or FFT_EHIP.
+ */
+int fft_execute_scratch(fft_plan* plan, const void* in, void* out, void* stream);
+
 /* Frees the plan.  A two-pass plan first waits for its last execution (its
  * workspace may still be in use); a single-pass plan holds no device memory
  * that its launches read or write (twiddle tables are shared and live until

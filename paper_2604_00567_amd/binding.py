@@ -47,6 +47,7 @@ _SIGS = {
     "fft_plan_create": ([_i64, _i64, _int, _int], _vp),
     "fft_plan_create_variant": ([_i64, _i64, _int, _int, _int, _int, _int], _vp),
     "fft_execute": ([_vp, _vp, _vp, _vp], _int),
+    "fft_execute_scratch": ([_vp, _vp, _vp, _vp], _int),
     "fft_destroy": ([_vp], None),
     "fft_table_build": ([_i64, _int, _int, _vp, _vp, _vp], _int),
     "fft_table_build_dir": ([_i64, _int, _int, _int, _vp, _vp, _vp], _int),
@@ -138,6 +139,10 @@ def fft_plan_create_variant(n: int, batch: int, dtype, kind, variant_a: int = 0,
 
 def fft_execute(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
     _check(_lib.fft_execute(plan, in_ptr, out_ptr, stream))
+
+
+def fft_execute_scratch(plan: int, in_ptr: int, out_ptr: int, stream: int = 0) -> None:
+    _check(_lib.fft_execute_scratch(plan, in_ptr, out_ptr, stream))
 
 
 def fft_destroy(plan: int) -> None:
@@ -336,6 +341,12 @@ class Plan:
         _check_tensor(x, self.n, self.batch, self.dtype)
         _check_tensor(y, self.n, self.batch, self.dtype)
         fft_execute(self.handle, x.data_ptr(), y.data_ptr(), _torch_stream(stream))
+
+    def execute_scratch(self, x, y, stream=None) -> None:
+        """fft_execute_scratch: the same transform with no device allocation."""
+        _check_tensor(x, self.n, self.batch, self.dtype)
+        _check_tensor(y, self.n, self.batch, self.dtype)
+        fft_execute_scratch(self.handle, x.data_ptr(), y.data_ptr(), _torch_stream(stream))
 
     def info(self) -> dict:
         return fft_plan_info(self.handle)

@@ -201,7 +201,9 @@ void size_workspace(fft_plan* p) {
     p->ws_need = (size_t)chunk * per;
 }
 
-int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
+// The plan's launches with the two-pass intermediate in `ws`, `chunk`
+// transforms at a time (fft_execute: the plan's workspace and chunk).
+int launch_plan_ws(const fft_plan* p, const void* in, void* out, hipStream_t s, void* ws, int64_t chunk) {
     const void* lt = p->table->ptr;
     if (!p->k2) {
         const bool aligned16 = (((uintptr_t)in | (uintptr_t)out) & 15) == 0;
@@ -212,16 +214,20 @@ int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
     }
     const int m1 = p->k1->log_nu, m2 = p->k2->log_nu;
     const size_t eb = (size_t)elem_bytes(p->dtype);
-    for (int64_t b0 = 0; b0 < p->batch; b0 += p->chunk) {
-        const int64_t nb = std::min<int64_t>(p->chunk, p->batch - b0);
+    for (int64_t b0 = 0; b0 < p->batch; b0 += chunk) {
+        const int64_t nb = std::min<int64_t>(chunk, p->batch - b0);
         const char* src = (const char*)in + (size_t)b0 * p->n * eb;
         char* dst = (char*)out + (size_t)b0 * p->n * eb;
-        hipError_t e = p->k1->launch(src, p->ws, lt, nb << m2, m2, s);
+        hipError_t e = p->k1->launch(src, ws, lt, nb << m2, m2, s);
         if (e != hipSuccess) return hip_error(e, "launch(cols)");
-        e = p->k2->launch(p->ws, dst, lt, nb << m1, m1, s);
+        e = p->k2->launch(ws, dst, lt, nb << m1, m1, s);
         if (e != hipSuccess) return hip_error(e, "launch(rows)");
     }
     return FFT_OK;
+}
+
+int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
+    return launch_plan_ws(p, in, out, s, p->ws, p->chunk);
 }
 
 static bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
@@ -292,7 +298,7 @@ static bool ranges_partially_overlap(const void* a, const void* b, size_t bytes)
     return x < y + bytes && y < x + bytes;
 }
 
-int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s) {
+int check_execute_args(const fft_plan* p, const void* in, const void* out) {
     if (!p) return set_error(FFT_EINVAL, "null plan");
     if (!in || !out) return set_error(FFT_EINVAL, "null data pointer");
     const size_t eb = (size_t)elem_bytes(p->dtype);
@@ -300,7 +306,13 @@ int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s) {
         return set_error(FFT_EINVAL, "data pointers must be aligned to the element size");
     if (ranges_partially_overlap(in, out, (size_t)p->n * p->batch * eb))
         return set_error(FFT_EINVAL, "in and out partially overlap");
-    int rc = launch_plan(p, in, out, s);
+    return FFT_OK;
+}
+
+int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s) {
+    int rc = check_execute_args(p, in, out);
+    if (rc != FFT_OK) return rc;
+    rc = launch_plan(p, in, out, s);
     if (rc != FFT_OK) return rc;
     // Only a two-pass plan holds memory that its launches use and that it may
     // free or replace (the workspace), so only its last launch is tracked;

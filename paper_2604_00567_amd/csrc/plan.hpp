@@ -50,4 +50,8 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
                       bool inverse = false);
 bool tuned_choice(int dtype, int log_n, int* variants);
 int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
+// Argument checks of an execute (null, alignment, partial overlap).
+int check_execute_args(const fft_plan* p, const void* in, const void* out);
+// The plan's launches with its two-pass intermediate in ws, chunk transforms at a time.
+int launch_plan_ws(const fft_plan* p, const void* in, void* out, hipStream_t s, void* ws, int64_t chunk);
 }  // namespace dsfft
