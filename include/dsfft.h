@@ -199,6 +199,45 @@ fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft
                                   int variant_a, int variant_b, int two_pass);
 
 /*
+ * Radix-4 form of the method (Sec. VI, generality: in a radix-r butterfly each
+ * twiddle multiplication picks its own bounded-ratio factorisation).  A plan
+ * for the same transform computed in the canonical radix-4 order: when log2 n
+ * is odd, one radix-2 stage of span 2 (the six-FMA butterfly of W^0) comes
+ * first; then radix-4 Stockham DIT stages of span L = 4, 16, ... (or 8, 32,
+ * ...) up to n.  The stage of span L combines, for r < n/L and j < L/4, the
+ * four span-L/4 results a, b, c, d at residues r + p n/L (p < 4) into
+ *   Y[r][j] = (a + W2 c) + (W1 b + W3 d),    Y[r][j + L/2]  = (a + W2 c) - (W1 b + W3 d),
+ *   Y[r][j + L/4] = (a - W2 c) - i (W1 b - W3 d), Y[r][j + 3L/4] = (a - W2 c) + i (W1 b - W3 d)
+ * (W1 = W_L^j, W2 = W1^2, W3 = W1^3; the inverse swaps the last two places)
+ * with 22 FMAs, each rounded once: W^k x = m_k h_k(x) through the table entry
+ * of W^k (mult m_k, ratio t_k, path by Algorithm 1's rules for `kind`; two FMAs
+ * each), u = a +- m2 h_c, and the odd pair W1 b +- W3 d = M (h_big +- rho
+ * h_small) with M the larger of |m1|, |m3| and rho = smaller / larger computed
+ * in FP64 and rounded once (|rho| <= 1), then Y = u +- M g.  Results differ
+ * from the radix-2 plans (another rounding order); they equal the oracle's
+ * radix-4 emulation bit for bit.  Whole transforms only: n = 2 .. 2^13
+ * (FFT_EUNSUPPORTED beyond, and for FFT_F16_F32).  `variant` = -1 takes the
+ * default configuration, else the variant-th radix-4 configuration of the
+ * size (fft_config_count_radix4).  Executed with fft_execute.  NULL on error.
+ */
+fft_plan* fft_plan_create_radix4(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                                 int direction, int variant);
+
+/* Number of compiled radix-4 configurations for (n, dtype). */
+int fft_config_count_radix4(int64_t n, fft_dtype dtype, int* count);
+
+/*
+ * Host-only radix-4 table export for size n (4 <= n <= 2^20, power of two):
+ * mult_out / ratio_out / path_out receive the rounded entries of W^k for
+ * k < 3n/4 (as fft_table_build, which stops at n/2), rho_out / sel_out per
+ * column j < n/4 of the last stage the rounded rho and the choice of the outer
+ * multiplier (1: m(W^j), 0: m(W^3j)).  Any output pointer may be NULL.
+ */
+int fft_table_build_radix4(int64_t n, fft_dtype dtype, fft_table_kind kind, int direction,
+                           void* mult_out, void* ratio_out, uint8_t* path_out, void* rho_out,
+                           uint8_t* sel_out);
+
+/*
  * Autotuner: times every compiled configuration for (n, dtype) -- register-
  * pass radices (fusion depth), units per workgroup (LDS tile), elements per
  * lane (waves per transform), LDS staging, cross-lane tail, single-kernel or

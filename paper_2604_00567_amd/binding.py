@@ -52,6 +52,9 @@ _SIGS = {
     "fft_table_build": ([_i64, _int, _int, _vp, _vp, _vp], _int),
     "fft_table_build_dir": ([_i64, _int, _int, _int, _vp, _vp, _vp], _int),
     "fft_plan_create_dir": ([_i64, _i64, _int, _int, _int], _vp),
+    "fft_plan_create_radix4": ([_i64, _i64, _int, _int, _int, _int], _vp),
+    "fft_config_count_radix4": ([_i64, _int, ctypes.POINTER(_int)], _int),
+    "fft_table_build_radix4": ([_i64, _int, _int, _int, _vp, _vp, _vp, _vp, _vp], _int),
     "fft_plan_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_int),
                        ctypes.POINTER(_int), ctypes.c_char_p, _sz], _int),
     "fft_plan_workspace_bytes": ([_vp, ctypes.POINTER(_sz)], _int),
@@ -162,6 +165,36 @@ def fft_table_build(n: int, dtype, kind, direction="forward"):
     if dt == FFT_F16:
         mult, ratio = mult.view(np.float16), ratio.view(np.float16)
     return mult, ratio, path
+
+
+def fft_table_build_radix4(n: int, dtype, kind, direction="forward"):
+    """Radix-4 export (host only): (mult, ratio, path) of W^k for k < 3n/4 and
+    (rho, sel) per column j < n/4 of the last stage, rounded to dtype."""
+    dt = _dt(dtype)
+    st = np.uint16 if dt == FFT_F16 else np.float32
+    k3, k1 = 3 * n // 4, n // 4
+    mult, ratio, path = np.empty(k3, st), np.empty(k3, st), np.empty(k3, np.uint8)
+    rho, sel = np.empty(k1, st), np.empty(k1, np.uint8)
+    _check(_lib.fft_table_build_radix4(n, dt, _kd(kind), _dir(direction), mult.ctypes.data,
+                                       ratio.ctypes.data, path.ctypes.data, rho.ctypes.data,
+                                       sel.ctypes.data))
+    if dt == FFT_F16:
+        mult, ratio, rho = mult.view(np.float16), ratio.view(np.float16), rho.view(np.float16)
+    return mult, ratio, path, rho, sel
+
+
+def fft_plan_create_radix4(n: int, batch: int, dtype, kind, direction="forward",
+                           variant: int = -1) -> int:
+    h = _lib.fft_plan_create_radix4(n, batch, _dt(dtype), _kd(kind), _dir(direction), variant)
+    if not h:
+        raise FFTError(FFT_EUNSUPPORTED, fft_last_error())
+    return h
+
+
+def fft_config_count_radix4(n: int, dtype) -> int:
+    c = _int()
+    _check(_lib.fft_config_count_radix4(n, _dt(dtype), ctypes.byref(c)))
+    return c.value
 
 
 def fft_plan_info(plan: int) -> dict:
@@ -327,10 +360,15 @@ class Plan:
     """Owns a plan handle; execute() takes torch tensors laid out (batch, n, 2)."""
 
     def __init__(self, n: int, batch: int, dtype="f16", kind="dual_select", variant=None,
-                 direction="forward"):
+                 direction="forward", radix: int = 2):
         self.n, self.batch, self.dtype, self.kind = n, batch, _dt(dtype), _kd(kind)
         self.direction = _dir(direction)
-        if variant is None:
+        if radix == 4:
+            self.handle = fft_plan_create_radix4(n, batch, self.dtype, self.kind, self.direction,
+                                                 -1 if variant is None else int(variant))
+        elif radix != 2:
+            raise FFTError(FFT_EINVAL, "radix must be 2 or 4")
+        elif variant is None:
             self.handle = fft_plan_create_dir(n, batch, self.dtype, self.kind, self.direction)
         elif self.direction == FFT_FORWARD:
             self.handle = fft_plan_create_variant(n, batch, self.dtype, self.kind, *variant)

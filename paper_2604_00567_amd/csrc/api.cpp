@@ -46,19 +46,20 @@ static std::map<std::tuple<int, int, int, int>, std::shared_ptr<DeviceTable>> g_
 // holding the old one keep it alive.
 static std::vector<std::shared_ptr<DeviceTable>> g_retired_tables;
 
-int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out) {
+int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out, int radix) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     std::lock_guard<std::mutex> lock(g_table_mu);
-    auto key = std::make_tuple(dev, dtype, kind, (int)inverse);
+    auto key = std::make_tuple(dev, dtype, kind, (int)inverse | (radix == 4 ? 2 : 0));
     auto it = g_tables.find(key);
     if (it != g_tables.end() && it->second->ncap >= n) {
         *out = it->second;
         return FFT_OK;
     }
     const int64_t ncap = std::max<int64_t>(n, kMinTableEntries);
-    std::vector<uint8_t> img = build_level_table(ncap, dtype, kind, inverse);
+    std::vector<uint8_t> img = radix == 4 ? build_level_table4(ncap, dtype, kind, inverse)
+                                          : build_level_table(ncap, dtype, kind, inverse);
     auto t = std::make_shared<DeviceTable>();
     t->ncap = ncap;
     t->bytes = img.size();
@@ -88,12 +89,13 @@ static const KernelCfg* table_for(int dtype, int* count) {
                            : (dtype == DT_F32 ? kernel_table_f32(count) : kernel_table_f16f32(count));
 }
 
-const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant) {
+const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant, bool radix4) {
     int cnt = 0;
     const KernelCfg* t = table_for(dtype, &cnt);
     int seen = 0;
     for (int i = 0; i < cnt; ++i) {
         if (t[i].mode != mode || t[i].log_nu != log_nu) continue;
+        if ((t[i].encoding == ENC_RADIX4) != radix4) continue;
         if (t[i].lds_bytes > 160 * 1024) continue;
         if (seen++ == variant) return &t[i];
     }
@@ -102,16 +104,16 @@ const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant) {
 
 // First configuration of (dtype, mode, log_nu) that does not stage through
 // LDS with 16-byte accesses (used when data pointers are not 16-byte aligned).
-const KernelCfg* find_plain_kernel(int dtype, int mode, int log_nu) {
+const KernelCfg* find_plain_kernel(int dtype, int mode, int log_nu, bool radix4 = false) {
     for (int v = 0;; ++v) {
-        const KernelCfg* k = find_kernel(dtype, mode, log_nu, v);
+        const KernelCfg* k = find_kernel(dtype, mode, log_nu, v, radix4);
         if (!k || !k->staged) return k;
     }
 }
 
-int count_kernels(int dtype, int mode, int log_nu) {
+int count_kernels(int dtype, int mode, int log_nu, bool radix4) {
     int n = 0;
-    while (find_kernel(dtype, mode, log_nu, n)) ++n;
+    while (find_kernel(dtype, mode, log_nu, n, radix4)) ++n;
     return n;
 }
 
@@ -125,7 +127,8 @@ std::string describe(const KernelCfg* k) {
                   k->staged, k->lane_tail, k->pipelined, k->threads, k->lds_bytes);
     std::string d = buf;
     if (k->upl > 1) d += ",upl=" + std::to_string(k->upl);
-    if (k->encoding) d += k->encoding == 1 ? ",enc=select" : ",enc=branch";
+    if (k->encoding == ENC_RADIX4) d += ",radix4";
+    else if (k->encoding) d += k->encoding == ENC_SELECT ? ",enc=select" : ",enc=branch";
     return d;
 }
 
@@ -163,6 +166,14 @@ static void small_batch_choice(fft_plan* p) {
 int choose_schedule(fft_plan* p, const int* variants) {
     const int m = p->log_n;
     const int v0 = variants ? variants[0] : 0, v1 = variants ? variants[1] : 0;
+    if (p->radix == 4) {
+        // the radix-4 form runs whole transforms only
+        p->k1 = find_kernel(p->dtype, MODE_SMALL, m, v0, true);
+        p->k1_plain = find_plain_kernel(p->dtype, MODE_SMALL, m, true);
+        p->k2 = nullptr;
+        if (!p->k1 || !p->k1_plain) return set_error(FFT_EUNSUPPORTED, "no radix-4 kernel for this size and dtype");
+        return FFT_OK;
+    }
     if (m <= small_limit(p->dtype) && (!variants || variants[2] == 0)) {
         p->k1 = find_kernel(p->dtype, MODE_SMALL, m, v0);
         p->k1_plain = find_plain_kernel(p->dtype, MODE_SMALL, m);
@@ -233,7 +244,7 @@ int launch_plan(fft_plan* p, const void* in, void* out, hipStream_t s) {
 static bool is_pow2(int64_t n) { return n >= 2 && (n & (n - 1)) == 0; }
 
 fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants,
-                      bool inverse) {
+                      bool inverse, int radix) {
     if (!is_pow2(n) || n > (int64_t(1) << 20)) {
         set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
         return nullptr;
@@ -256,6 +267,7 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
     p->dtype = dtype;
     p->kind = kind;
     p->inverse = inverse;
+    p->radix = radix;
     p->log_n = 0;
     while ((int64_t(1) << p->log_n) < n) ++p->log_n;
     hipError_t e = hipGetDevice(&p->device);
@@ -263,16 +275,16 @@ fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* 
         hip_error(e, "hipGetDevice");
         return nullptr;
     }
-    if (get_table(n, table_dtype(dtype), kind, inverse, &p->table) != FFT_OK) return nullptr;
+    if (get_table(n, table_dtype(dtype), kind, inverse, &p->table, radix) != FFT_OK) return nullptr;
     int tuned[3];
-    if (!variants && tuned_choice(dtype, p->log_n, tuned)) {
+    if (!variants && radix == 2 && tuned_choice(dtype, p->log_n, tuned)) {
         // a recorded tuning choice; fall back to the fixed rule if it no longer exists
         if (choose_schedule(p.get(), tuned) != FFT_OK && choose_schedule(p.get(), nullptr) != FFT_OK)
             return nullptr;
     } else if (choose_schedule(p.get(), variants) != FFT_OK) {
         return nullptr;
     }
-    if (!variants) small_batch_choice(p.get());
+    if (!variants && radix == 2) small_batch_choice(p.get());
     size_workspace(p.get());
     if (p->ws_need) {
         e = hipMalloc(&p->ws, p->ws_need);
@@ -414,6 +426,48 @@ int fft_plan_set_workspace(fft_plan* p, void* dev_ptr, size_t bytes) {
 }  // extern "C"
 
 extern "C" {
+
+fft_plan* fft_plan_create_radix4(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
+                                 int direction, int variant) {
+    if (direction != FFT_FORWARD && direction != FFT_INVERSE) {
+        set_error(FFT_EINVAL, "direction must be FFT_FORWARD or FFT_INVERSE");
+        return nullptr;
+    }
+    if ((int)dtype == DT_F16F32) {
+        set_error(FFT_EUNSUPPORTED, "the radix-4 form takes FFT_F16 or FFT_F32");
+        return nullptr;
+    }
+    if (variant < -1) {
+        set_error(FFT_EINVAL, "variant must be -1 (default) or a configuration index");
+        return nullptr;
+    }
+    const int v[3] = {variant < 0 ? 0 : variant, 0, 0};
+    return plan_create(n, batch, (int)dtype, (int)kind, v, direction == FFT_INVERSE, 4);
+}
+
+int fft_config_count_radix4(int64_t n, fft_dtype dtype, int* count) {
+    if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
+        return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
+    if (!count) return set_error(FFT_EINVAL, "null argument");
+    int m = 0;
+    while ((int64_t(1) << m) < n) ++m;
+    *count = (int)dtype == DT_F16F32 ? 0 : count_kernels((int)dtype, MODE_SMALL, m, true);
+    return FFT_OK;
+}
+
+int fft_table_build_radix4(int64_t n, fft_dtype dtype, fft_table_kind kind, int direction,
+                           void* mult_out, void* ratio_out, uint8_t* path_out, void* rho_out,
+                           uint8_t* sel_out) {
+    if (n < 4 || (n & (n - 1)) || n > (int64_t(1) << 20))
+        return set_error(FFT_EINVAL, "n must be a power of two in [4, 2^20]");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32) return set_error(FFT_EINVAL, "bad dtype");
+    if ((int)kind < 0 || (int)kind > 3) return set_error(FFT_EINVAL, "bad table kind");
+    if (direction != FFT_FORWARD && direction != FFT_INVERSE)
+        return set_error(FFT_EINVAL, "direction must be FFT_FORWARD or FFT_INVERSE");
+    build_flat_table4(n, (int)dtype, (int)kind, direction == FFT_INVERSE, mult_out, ratio_out, path_out,
+                      rho_out, sel_out);
+    return FFT_OK;
+}
 
 fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
                                   int variant_a, int variant_b, int two_pass) {

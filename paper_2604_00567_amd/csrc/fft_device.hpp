@@ -105,7 +105,11 @@ __device__ __forceinline__ void bfly(f2_t& a, f2_t& b, const TwF tw) {
 //               code (lanes of one wave on both paths run both).
 // All three compute the same FMAs on the same operands (bit-identical);
 // binary16 kernels only (the binary32 butterfly always uses a lane mask).
-enum { ENC_TABLE = 0, ENC_SELECT = 1, ENC_BRANCH = 2 };
+//   ENC_RADIX4  not a path encoding: the radix-4 form of the method (Sec. VI,
+//               generality), whose butterflies combine four inputs with 22
+//               FMAs and read radix-4 table entries (Tw4H / Tw4F); a
+//               different canonical order, so results differ from radix 2.
+enum { ENC_TABLE = 0, ENC_SELECT = 1, ENC_BRANCH = 2, ENC_RADIX4 = 3 };
 
 template <int ENC>
 __device__ __forceinline__ void bfly_enc(uint32_t& a, uint32_t& b, const TwH tw) {
@@ -161,6 +165,148 @@ template <class E> struct TwOf;
 template <> struct TwOf<uint32_t> { using type = TwH; };
 template <> struct TwOf<f2_t> { using type = TwF; };
 
+// ------------------------------------------------------- radix-4 butterflies
+//
+// Radix-4 form of the method (Sec. VI: in a higher-radix butterfly each
+// twiddle multiplication picks its own bounded-ratio factorisation).  A
+// radix-4 stage of span L combines, for column j < L/4, the four span-L/4
+// DFTs a, b, c, d at residues r + p N/L with W1 = W_L^j, W2 = W1^2, W3 = W1^3:
+//   Y0 = (a + W2 c) + (W1 b + W3 d),   Y2 = (a + W2 c) - (W1 b + W3 d),
+//   Y1 = (a - W2 c) - j (W1 b - W3 d), Y3 = (a - W2 c) + j (W1 b - W3 d)
+// (Y_p at column j + p L/4).  Each W^k of the three takes its own table entry
+// (m_k, t_k, path_k) by the rules of Algorithm 1, and W^k x = m_k h_k(x) with
+//   h = (x_r - t x_i, t x_r + x_i)        cosine path (eq. (berg-s))
+//   h = (-(x_i - t x_r), x_r + t x_i)     sine path (eq. (lf-s), s1 negated).
+// The odd pair W1 b +- W3 d = m1 h_b +- m3 h_d takes the larger of |m1|, |m3|
+// as outer multiplier M and rho = smaller/larger (|rho| <= 1, like every
+// ratio):  |m1| >= |m3|: g0 = h_b + rho h_d, g1 = h_b - rho h_d (M = m1);
+//          otherwise:    g0 = rho h_b + h_d, g1 = rho h_b - h_d (M = m3).
+// Then u0 = a + m2 h_c, u1 = a - m2 h_c, Y0/Y2 = u0 +- M g0,
+// Y1 = (u1_r + M g1_i, u1_i - M g1_r), Y3 = (u1_r - M g1_i, u1_i + M g1_r):
+// 22 FMAs, each rounded once (two radix-2 stages take 24).
+//
+// Device form.  With s_x = (x.lo - t x.hi, t x.lo + x.hi) of the path-ordered
+// operand (as in the radix-2 butterfly) h = (sigma s.lo, s.hi), sigma = -1 on
+// the sine path.  Negation is exact (RN(-v) = -RN(v)), so every sign folds
+// into the table's multipliers: with (x, y) = (s_d, s_b) when M = m1 and
+// (s_b, s_d) otherwise,
+//   g0' = y + (sigma1 sigma3 rho, rho) x,   g1'' = y - (sigma1 sigma3 rho, rho) x,
+//   g0 = D g0',  g1 = sg D g1''   (D = diag(sigma_M, 1), sg = +1 when M = m1, -1 otherwise),
+//   Y0 = u0 + (sigma_M M, M) g0',  Y2 = u0 - (sigma_M M, M) g0',
+//   Y1 = u1 + (sg M, -sg sigma_M M) g1''.yx,  Y3 = u1 - (sg M, -sg sigma_M M) g1''.yx,
+// which are the same FMAs on the same operands as the definition.  The
+// inverse transform (conjugate twiddles) swaps the places of Y1 and Y3; the
+// inverse table stores the last multiplier negated, which makes that swap.
+//
+// Radix-4 table: entry L/4 + j holds the butterfly of span L, column j
+// (L = 4, 8, 16, ...: every level fits in [1, N_cap/2)); entry 0 holds the
+// radix-2 butterfly of W^0 in (ts1, w2), for the span-2 stage that comes first
+// when log2 N is odd.
+struct __attribute__((aligned(16))) Tw4H {
+    uint32_t ts1, ts2, ts3;   // operand order | ratio << 16 of W1, W2, W3 (as TwH::ts)
+    uint32_t w2;              // (sigma2 m2, m2)
+    uint32_t rr;              // (sigma1 sigma3 rho, rho)
+    uint32_t mm0;             // (sigma_M M, M)
+    uint32_t mm1;             // (sg M, -sg sigma_M M), negated in the inverse table
+    uint32_t msel;            // all ones when M = m1
+};
+struct __attribute__((aligned(16))) Tw4F {
+    float t1, t2, t3;
+    uint32_t mask1, mask2, mask3;   // all ones on the sine path (as TwF::mask)
+    float sm2, m2;
+    float srho, rho;
+    float smM, M;
+    float mma, mmb;
+    uint32_t msel, pad;
+};
+
+// s = (c.lo - t c.hi, t c.lo + c.hi) of the path-ordered operand c.
+__device__ __forceinline__ h2_t scaled_pair(uint32_t b, uint32_t ts) {
+    const h2_t cv = as_h2(__builtin_amdgcn_alignbit(b, b, ts));
+    const h2_t tv = as_h2(ts);
+    h2_t tt;
+    tt.x = -tv.y;
+    tt.y = tv.y;
+    return __builtin_elementwise_fma(tt, cv.yx, cv);
+}
+__device__ __forceinline__ f2_t scaled_pair(f2_t b, float t, uint32_t mask) {
+    const float bxf = b.x, byf = b.y;
+    const uint32_t br = __builtin_bit_cast(uint32_t, bxf);
+    const uint32_t bi = __builtin_bit_cast(uint32_t, byf);
+    const float cr = __builtin_bit_cast(float, (mask & bi) | (~mask & br));
+    const float ci = __builtin_bit_cast(float, (mask & br) | (~mask & bi));
+    f2_t s;
+    s.x = __builtin_fmaf(-t, ci, cr);
+    s.y = __builtin_fmaf(t, cr, ci);
+    return s;
+}
+__device__ __forceinline__ uint32_t bitsel(uint32_t m, uint32_t x, uint32_t y) { return (m & x) | (~m & y); }
+
+// Radix-4 butterfly, binary16: 11 packed FMAs (22 FMAs); (a, b, c, d) -> (Y0, Y1, Y2, Y3).
+__device__ __forceinline__ void bfly4(uint32_t& a, uint32_t& b, uint32_t& c, uint32_t& d, const Tw4H& w) {
+    const h2_t sb = scaled_pair(b, w.ts1);
+    const h2_t sc = scaled_pair(c, w.ts2);
+    const h2_t sd = scaled_pair(d, w.ts3);
+    const h2_t av = as_h2(a);
+    const h2_t w2 = as_h2(w.w2);
+    const h2_t u0 = __builtin_elementwise_fma(sc, w2, av);
+    const h2_t u1 = __builtin_elementwise_fma(-sc, w2, av);
+    const h2_t x = as_h2(bitsel(w.msel, as_u32(sd), as_u32(sb)));
+    const h2_t y = as_h2(bitsel(w.msel, as_u32(sb), as_u32(sd)));
+    const h2_t rr = as_h2(w.rr);
+    const h2_t g0 = __builtin_elementwise_fma(x, rr, y);
+    const h2_t g1 = __builtin_elementwise_fma(-x, rr, y);
+    const h2_t mm0 = as_h2(w.mm0), mm1 = as_h2(w.mm1);
+    a = as_u32(__builtin_elementwise_fma(g0, mm0, u0));
+    c = as_u32(__builtin_elementwise_fma(-g0, mm0, u0));
+    b = as_u32(__builtin_elementwise_fma(g1.yx, mm1, u1));
+    d = as_u32(__builtin_elementwise_fma(-g1.yx, mm1, u1));
+}
+
+// Radix-4 butterfly, binary32: 22 v_fma_f32.
+__device__ __forceinline__ void bfly4(f2_t& a, f2_t& b, f2_t& c, f2_t& d, const Tw4F& w) {
+    const f2_t sb = scaled_pair(b, w.t1, w.mask1);
+    const f2_t sc = scaled_pair(c, w.t2, w.mask2);
+    const f2_t sd = scaled_pair(d, w.t3, w.mask3);
+    const float ax = a.x, ay = a.y;
+    const float u0x = __builtin_fmaf(sc.x, w.sm2, ax), u0y = __builtin_fmaf(sc.y, w.m2, ay);
+    const float u1x = __builtin_fmaf(-sc.x, w.sm2, ax), u1y = __builtin_fmaf(-sc.y, w.m2, ay);
+    const float sbx = sb.x, sby = sb.y, sdx = sd.x, sdy = sd.y;
+    const uint32_t bx = __builtin_bit_cast(uint32_t, sbx), by = __builtin_bit_cast(uint32_t, sby);
+    const uint32_t dx = __builtin_bit_cast(uint32_t, sdx), dy = __builtin_bit_cast(uint32_t, sdy);
+    const float xx = __builtin_bit_cast(float, bitsel(w.msel, dx, bx));
+    const float xy = __builtin_bit_cast(float, bitsel(w.msel, dy, by));
+    const float yx = __builtin_bit_cast(float, bitsel(w.msel, bx, dx));
+    const float yy = __builtin_bit_cast(float, bitsel(w.msel, by, dy));
+    const float g0x = __builtin_fmaf(xx, w.srho, yx), g0y = __builtin_fmaf(xy, w.rho, yy);
+    const float g1x = __builtin_fmaf(-xx, w.srho, yx), g1y = __builtin_fmaf(-xy, w.rho, yy);
+    f2_t y0, y1, y2, y3;
+    y0.x = __builtin_fmaf(g0x, w.smM, u0x);
+    y0.y = __builtin_fmaf(g0y, w.M, u0y);
+    y2.x = __builtin_fmaf(-g0x, w.smM, u0x);
+    y2.y = __builtin_fmaf(-g0y, w.M, u0y);
+    y1.x = __builtin_fmaf(g1y, w.mma, u1x);
+    y1.y = __builtin_fmaf(g1x, w.mmb, u1y);
+    y3.x = __builtin_fmaf(-g1y, w.mma, u1x);
+    y3.y = __builtin_fmaf(-g1x, w.mmb, u1y);
+    a = y0;
+    b = y1;
+    c = y2;
+    d = y3;
+}
+
+// The radix-2 butterfly of the span-2 stage (odd log2 N) from entry 0.
+__device__ __forceinline__ void bfly_w0(uint32_t& a, uint32_t& b, const Tw4H& w) { bfly(a, b, TwH{w.w2, w.ts1}); }
+__device__ __forceinline__ void bfly_w0(f2_t& a, f2_t& b, const Tw4F& w) {
+    bfly(a, b, TwF{w.sm2, w.m2, w.t1, w.mask1});
+}
+
+// Table entry type of a kernel: radix-2 entries, or radix-4 ones (ENC_RADIX4).
+template <class E, int ENC> struct TwOfEnc { using type = typename TwOf<E>::type; };
+template <> struct TwOfEnc<uint32_t, ENC_RADIX4> { using type = Tw4H; };
+template <> struct TwOfEnc<f2_t, ENC_RADIX4> { using type = Tw4F; };
+template <class E, int ENC> using TwT = typename TwOfEnc<E, ENC>::type;
+
 // Storage and compute types.  A kernel computes in E; its input and output
 // may be stored in another type S (binary16 storage with binary32
 // butterflies: S = binary16 pair, E = binary32 pair).  Loads widen exactly,
@@ -213,26 +359,72 @@ __device__ __forceinline__ void store_elem(E v, S* p) {
 // (1..LR) pairs v[i + 2He] with v[i + H + 2He] (H = R >> t, i < H, e < 2^(t-1))
 // under twiddle c = 2^(t-1) + e, and writes A to v[i + He], B to v[i + He + R/2].
 // On entry v[i] = Y[r + M i][q]; on exit v[e] = Y'[r][q + L0 e].
-template <int LR, int ENC = ENC_TABLE, class E, class TW>
-__device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
+// Radix-4 form: the same group layout, radix-4 stages (and, for the first pass
+// of an odd log2 N, the span-2 radix-2 stage before them).  With S columns
+// done (H = R / S residues left), v[i + H e] holds residue i, column e; a
+// radix-4 stage takes a, b, c, d = v[i + H e + p H/4] (p < 4) under entry
+// c = S + e and writes output p to v[i + (H/4) (e + p S)].
+template <int LR, bool ODD, class E, class TW>
+__device__ __forceinline__ void reg_pass4(E* v, const TW* tw) {
     constexpr int R = 1 << LR;
-#pragma unroll
-    for (int t = 1; t <= LR; ++t) {
-        const int H = R >> t;
+    static_assert((LR - (ODD ? 1 : 0)) % 2 == 0, "radix-4 stages fill the pass");
+    if constexpr (ODD) {
         E nv[R];
 #pragma unroll
-        for (int e = 0; e < (1 << (t - 1)); ++e) {
+        for (int i = 0; i < R / 2; ++i) {
+            E a = v[i], b = v[i + R / 2];
+            bfly_w0(a, b, tw[0]);
+            nv[i] = a;
+            nv[i + R / 2] = b;
+        }
 #pragma unroll
-            for (int i = 0; i < H; ++i) {
-                E a = v[i + 2 * H * e];
-                E b = v[i + H + 2 * H * e];
-                bfly_enc<ENC>(a, b, tw[(1 << (t - 1)) + e]);
-                nv[i + H * e] = a;
-                nv[i + H * e + R / 2] = b;
+        for (int k = 0; k < R; ++k) v[k] = nv[k];
+    }
+#pragma unroll
+    for (int S = ODD ? 2 : 1; S < R; S *= 4) {
+        const int H = R / S, H4 = H / 4;
+        E nv[R];
+#pragma unroll
+        for (int e = 0; e < S; ++e) {
+#pragma unroll
+            for (int i = 0; i < H4; ++i) {
+                E a = v[i + H * e], b = v[i + H4 + H * e], c = v[i + 2 * H4 + H * e], d = v[i + 3 * H4 + H * e];
+                bfly4(a, b, c, d, tw[S + e]);
+                nv[i + H4 * e] = a;
+                nv[i + H4 * (e + S)] = b;
+                nv[i + H4 * (e + 2 * S)] = c;
+                nv[i + H4 * (e + 3 * S)] = d;
             }
         }
 #pragma unroll
         for (int k = 0; k < R; ++k) v[k] = nv[k];
+    }
+}
+
+template <int LR, int ENC = ENC_TABLE, bool ODD = false, class E, class TW>
+__device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
+    if constexpr (ENC == ENC_RADIX4) {
+        reg_pass4<LR, ODD>(v, tw);
+    } else {
+        constexpr int R = 1 << LR;
+#pragma unroll
+        for (int t = 1; t <= LR; ++t) {
+            const int H = R >> t;
+            E nv[R];
+#pragma unroll
+            for (int e = 0; e < (1 << (t - 1)); ++e) {
+#pragma unroll
+                for (int i = 0; i < H; ++i) {
+                    E a = v[i + 2 * H * e];
+                    E b = v[i + H + 2 * H * e];
+                    bfly_enc<ENC>(a, b, tw[(1 << (t - 1)) + e]);
+                    nv[i + H * e] = a;
+                    nv[i + H * e + R / 2] = b;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < R; ++k) v[k] = nv[k];
+        }
     }
 }
 
@@ -337,22 +529,22 @@ constexpr size_t lds_twiddle_offset() {
     return (unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E) + 15) / 16 * 16;
 }
 // LDS bytes of a workgroup: the exchange area, and with PIPE = 3, 4 or 5 the twiddle copy.
-template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
+template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP, int ENC = ENC_TABLE>
 constexpr size_t unit_lds_bytes() {
     constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() +
                        lds_row_twiddle_entries<MODE, UPW, PP, PIPE>();
     if (TE == 0) return unit_lds_elems<E, LOG_E, MODE, UPW, PP>() * sizeof(E);
-    return lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>() + (size_t)TE * sizeof(typename TwOf<E>::type);
+    return lds_twiddle_offset<E, LOG_E, MODE, UPW, PP>() + (size_t)TE * sizeof(TwT<E, ENC>);
 }
 // Whether a configuration fits a workgroup's LDS for element type E (the
 // configuration list serves both element sizes; entries that do not fit are
 // neither compiled nor offered).  PIPE = 3, 4 and 5 also need a pass to serve.
-template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP>
+template <class E, int LOG_NU, int LOG_E, int MODE, int UPW, int LANE, int PIPE, class PP, int ENC = ENC_TABLE>
 constexpr bool unit_fits() {
     if ((PIPE == 3 || PIPE == 4 || PIPE == 5) && lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PP, PIPE>() == 0 &&
         lds_row_twiddle_entries<MODE, UPW, PP, PIPE>() == 0)
         return false;
-    return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP>() <= kLdsBytes;
+    return unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PP, ENC>() <= kLdsBytes;
 }
 
 // ------------------------------------------------------------------ the kernel
@@ -573,9 +765,9 @@ __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
 // entry of butterfly index c (1 <= c < R) of group g + G u.  Entries depend on
 // the lane's position only, not on data.
 // (group_twiddles: the same for one group, tw[c].)
-template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P>
-__device__ __forceinline__ void group_twiddles(typename TwOf<E>::type* tw,
-                                               const typename TwOf<E>::type* __restrict__ lt,
+template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P,
+          int ENC = ENC_TABLE>
+__device__ __forceinline__ void group_twiddles(TwT<E, ENC>* tw, const TwT<E, ENC>* __restrict__ lt,
                                                const UnitGeom& geo0, int g, int u) {
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NU = 1 << LOG_NU;
@@ -585,9 +777,13 @@ __device__ __forceinline__ void group_twiddles(typename TwOf<E>::type* tw,
     constexpr int L0 = 1 << PP::log_l0(P);
     constexpr int LOGM = PP::log_m(P);
     const int q = (g + G * u) >> LOGM;        // column within the unit
+    // Radix-4 form: its stages read entries c = S + e < 2S <= R/2 only, and
+    // entry 0 is the span-2 stage's radix-2 butterfly.
+    constexpr int C0 = ENC == ENC_RADIX4 ? 0 : 1;
+    constexpr int C1 = ENC == ENC_RADIX4 ? R / 2 : R;
     if constexpr (P == 0 && MODE != MODE_ROWS) {
 #pragma unroll
-        for (int c = 1; c < R; ++c) tw[c] = lt[c];
+        for (int c = C0; c < C1; ++c) tw[c] = lt[c];
     } else if constexpr (MODE == MODE_SMALL && !LANE && LOGM >= 6 && G % 64 == 0) {
         // A wave's 64 lanes hold 64 consecutive groups (g = tid mod G, G a
         // multiple of 64), and with M >= 64 groups per column they share the
@@ -595,24 +791,24 @@ __device__ __forceinline__ void group_twiddles(typename TwOf<E>::type* tw,
         // cache, which keeps them off the vector memory path.
         const int qs = __builtin_amdgcn_readfirstlane(q);
 #pragma unroll
-        for (int c = 1; c < R; ++c) tw[c] = lt[qs + L0 * c];
+        for (int c = C0 > 0 ? C0 : 1; c < C1; ++c) tw[c] = lt[qs + L0 * c];
     } else {
         const int qg = geo0.q0 + (q << geo0.log_lb);
         const int lg0 = L0 << geo0.log_lb;
 #pragma unroll
-        for (int c = 1; c < R; ++c) tw[c] = lt[qg + lg0 * c];
+        for (int c = C0 > 0 ? C0 : 1; c < C1; ++c) tw[c] = lt[qg + lg0 * c];
     }
 }
-template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P>
-__device__ __forceinline__ void pass_twiddles(typename TwOf<E>::type* tw,
-                                              const typename TwOf<E>::type* __restrict__ lt,
+template <class E, int LOG_NU, int LOG_E, int MODE, int LR0, int LR1, int LR2, int LANE, int P,
+          int ENC = ENC_TABLE>
+__device__ __forceinline__ void pass_twiddles(TwT<E, ENC>* tw, const TwT<E, ENC>* __restrict__ lt,
                                               const UnitGeom& geo0, int g) {
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int R = 1 << PP::lr(P);
     constexpr int GPL = (1 << LOG_E) / R;
 #pragma unroll
     for (int u = 0; u < GPL; ++u)
-        group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw + u * R, lt, geo0, g, u);
+        group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P, ENC>(tw + u * R, lt, geo0, g, u);
 }
 
 // Twiddle prefetch (configurations with PIPE = 2): whole-transform units load
@@ -657,10 +853,10 @@ __device__ __forceinline__ void pin_twiddle(TwF& t) {
 // twiddles when the previous pass loaded them (twiddle_prefetch).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PRE, int P, class Geo, class SI, class SO>
-__device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::type* __restrict__ lt,
+__device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncoding>* __restrict__ lt,
                                           const SI* in, SO* out, const Geo& gp,
-                                          const typename TwOf<E>::type* twp = nullptr) {
-    using TW = typename TwOf<E>::type;
+                                          const TwT<E, Geo::kEncoding>* twp = nullptr) {
+    using TW = TwT<E, Geo::kEncoding>;
     using PP = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
     constexpr int NP = PP::NP;
     if constexpr (P < NP) {
@@ -710,7 +906,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
         constexpr int NEXT_TW = PFN ? (EL >> PP::lr(P + 1)) << PP::lr(P + 1) : 1;
         TW twn[NEXT_TW];
         if constexpr (PFN) {
-            pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P + 1>(twn, lt, geo0, g);
+            pass_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P + 1, Geo::kEncoding>(twn, lt, geo0, g);
             asm volatile("" ::: "memory");
         }
 
@@ -781,10 +977,12 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 #pragma unroll
                 for (int c = 1; c < R; ++c) tw[c] = ltp[q + L0 * c];
             } else {
-                group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P>(tw, lt, geo0, g, u);
+                group_twiddles<E, LOG_NU, LOG_E, MODE, LR0, LR1, LR2, LANE, P, Geo::kEncoding>(tw, lt, geo0, g, u);
             }
+            // radix-4 form: the first pass of an odd log2 N starts with the span-2 stage
+            constexpr bool ODD = Geo::kEncoding == ENC_RADIX4 && P == 0 && (LOG_NU & 1);
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding>(v + k * EL + u * R, tw);
+            for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding, ODD>(v + k * EL + u * R, tw);
         }
         if constexpr (PFN) {
             // entries c >= 1 of each group are the loaded ones
@@ -927,8 +1125,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const typename TwOf<E>::
 // MODE_SMALL.  Dynamic LDS: UPW * PassPlan::region() elements.
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE, class SI, class SO, int ENC>
-__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
-                                                 const typename TwOf<E>::type* __restrict__ lt,
+__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out, const TwT<E, ENC>* __restrict__ lt,
                                                  int64_t units, int log_m);
 
 // SI, SO: storage types of the input and output (E unless the plan stores
@@ -936,8 +1133,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE, class SI = E, class SO = E, int ENC = ENC_TABLE>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E))
-fft_unit_kernel(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
-                int64_t units, int log_m) {
+fft_unit_kernel(const SI* in, SO* out, const TwT<E, ENC>* __restrict__ lt, int64_t units, int log_m) {
     unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO, ENC>(
         in, out, lt, units, log_m);
 }
@@ -947,16 +1143,14 @@ fft_unit_kernel(const SI* in, SO* out, const typename TwOf<E>::type* __restrict_
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE, class SI = E, class SO = E, int ENC = ENC_TABLE>
 __global__ void __launch_bounds__((UPW / UPL) << (LOG_NU - LOG_E)) __attribute__((amdgpu_waves_per_eu(3)))
-fft_unit_kernel_pipe(const SI* in, SO* out, const typename TwOf<E>::type* __restrict__ lt,
-                     int64_t units, int log_m) {
+fft_unit_kernel_pipe(const SI* in, SO* out, const TwT<E, ENC>* __restrict__ lt, int64_t units, int log_m) {
     unit_kernel_body<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, SI, SO, ENC>(
         in, out, lt, units, log_m);
 }
 
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE, class SI, class SO, int ENC>
-__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
-                                                 const typename TwOf<E>::type* __restrict__ lt,
+__device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out, const TwT<E, ENC>* __restrict__ lt,
                                                  int64_t units, int log_m) {
     static_assert(LR0 + LR1 + LR2 + 2 * LANE == LOG_NU, "radices must multiply to NU");
     static_assert(LR0 <= LOG_E && LR1 <= LOG_E && LR2 <= LOG_E, "radix above elements per lane");
@@ -968,6 +1162,10 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
     static_assert((PIPE != 2 && PIPE != 5) || MODE == MODE_SMALL, "twiddle prefetch needs whole-transform units");
     static_assert((PIPE != 4 && PIPE != 5) || MODE != MODE_ROWS,
                   "LDS twiddles of later passes need units with their own table offsets");
+    static_assert(ENC != ENC_RADIX4 ||
+                      (MODE == MODE_SMALL && !LANE && PIPE != 1 && PIPE != 2 && PIPE != 5 &&
+                       LR0 % 2 == LOG_NU % 2 && LR1 % 2 == 0 && LR2 % 2 == 0),
+                  "radix-4 form: whole transforms whose passes start on radix-4 stage boundaries");
     E v[UPL << LOG_E];
     if constexpr (PIPE == 1) {
         // persistent: this workgroup takes blocks blockIdx.x, + gridDim.x, ...
@@ -1012,7 +1210,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             // entry per lane per step; the first pass reads them right after
             // its loads, so a barrier publishes them
             using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
-            using TW = typename TwOf<E>::type;
+            using TW = TwT<E, ENC>;
             constexpr int TE = lds_row_twiddle_entries<MODE, UPW, PPT, PIPE>();
             constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
             TW* dst = reinterpret_cast<TW*>(lds_raw + lds_twiddle_offset<E, LOG_E, MODE, UPW, PPT>());
@@ -1029,7 +1227,7 @@ __device__ __forceinline__ void unit_kernel_body(const SI* in, SO* out,
             // the barrier after the first exchange's writes orders it before
             // pass 1 reads it
             using PPT = PassPlan<LOG_NU, LR0, LR1, LR2, LANE>;
-            using TW = typename TwOf<E>::type;
+            using TW = TwT<E, ENC>;
             constexpr int TE = lds_twiddle_entries<LOG_NU, LOG_E, MODE, LANE, PPT, PIPE>();
             constexpr int CHUNKS = (int)(TE * sizeof(TW) / 16);
             constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);

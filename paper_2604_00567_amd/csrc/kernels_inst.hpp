@@ -32,10 +32,18 @@ template <class E, class S, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, i
 static constexpr bool cfg_fits() {
     if constexpr (!std::is_same_v<E, S>)
         if (STG || PIPE == 1) return false;
-    // the path-encoding variants: binary16 plans, plain (non-pipelined, no lane tail) kernels
-    if (ENC != ENC_TABLE && (!std::is_same_v<E, uint32_t> || !std::is_same_v<E, S> || PIPE == 1 || LANE))
+    // the radix-4 form: whole transforms stored as computed, no lane tail, no
+    // second register set or prefetch, passes on radix-4 stage boundaries
+    if (ENC == ENC_RADIX4) {
+        if (!std::is_same_v<E, S> || MODE != MODE_SMALL || LANE || PIPE == 1 || PIPE == 2 || PIPE == 5)
+            return false;
+        if (LR0 % 2 != LOG_NU % 2 || LR1 % 2 || LR2 % 2) return false;
+    } else if (ENC != ENC_TABLE &&
+               (!std::is_same_v<E, uint32_t> || !std::is_same_v<E, S> || PIPE == 1 || LANE)) {
+        // the path-encoding variants: binary16 plans, plain (non-pipelined, no lane tail) kernels
         return false;
-    return unit_fits<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
+    }
+    return unit_fits<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>, ENC>();
 }
 
 // The kernel of a configuration: the pipelined entry (with its occupancy
@@ -67,14 +75,14 @@ template <class E, class S, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, i
           int STG, int LANE, int PIPE, int ENC>
 static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t units, int log_m,
                               hipStream_t stream) {
-    using TW = typename TwOf<E>::type;
+    using TW = TwT<E, ENC>;
     using IO = IoOf<E, S, MODE>;
     if constexpr (!cfg_fits<E, S, LOG_NU, LOG_E, UPW, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>()) {
         return hipErrorInvalidConfiguration;
     } else {
         constexpr int NT = (UPW / UPL) << (LOG_NU - LOG_E);
         constexpr size_t LDS =
-            unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>();
+            unit_lds_bytes<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>, ENC>();
         auto kern = kernel_ptr<E, S, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>();
         int64_t grid = (units + UPW - 1) / UPW;
         if (grid <= 0) return hipSuccess;
@@ -107,7 +115,7 @@ static hipError_t launch_unit(const void* in, void* out, const void* lt, int64_t
      LOG_NU, LOG_E, UPW, UPL, {LR0, LR1, LR2}, STG, LANE, PIPE, ENC,                            \
      ((UPW) / (UPL)) << ((LOG_NU) - (LOG_E)),                                                  \
      unit_lds_bytes<ELEM_T, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE,                               \
-                    PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>(),                                  \
+                    PassPlan<LOG_NU, LR0, LR1, LR2, LANE>, ENC>(),                             \
      &launch_unit<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>, \
      kernel_entry<ELEM_T, STORE_T, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, STG, LANE, PIPE, ENC>()},
 #define CFGU(MODE, LOG_NU, LOG_E, UPW, LR0, LR1, LR2, STG, LANE, PIPE, UPL)                   \

@@ -19,10 +19,14 @@ struct DeviceTable {
 
 int set_error(int code, const std::string& msg);
 int hip_error(hipError_t e, const char* where);
-// The shared device table of (device, dtype, kind, direction) covering size n.
-int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out);
-const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant);
-int count_kernels(int dtype, int mode, int log_nu);
+// The shared device table of (device, dtype, kind, direction, radix) covering
+// size n (radix 2: level-ordered radix-2 entries; radix 4: the radix-4 form's).
+int get_table(int64_t n, int dtype, int kind, bool inverse, std::shared_ptr<DeviceTable>* out,
+              int radix = 2);
+// The variant-th compiled configuration of (dtype, mode, log_nu) among those
+// of the radix-2 butterflies (radix4 = false) or of the radix-4 form.
+const KernelCfg* find_kernel(int dtype, int mode, int log_nu, int variant, bool radix4 = false);
+int count_kernels(int dtype, int mode, int log_nu, bool radix4 = false);
 std::string describe(const KernelCfg* k);
 int elem_bytes(int dtype);
 int work_elem_bytes(int dtype);
@@ -33,6 +37,7 @@ struct fft_plan {
     int64_t n = 0, batch = 0;
     int log_n = 0, dtype = 0, kind = 0, device = 0;
     bool inverse = false;                   // inverse transform (conjugate tables)
+    int radix = 2;                          // 4: the radix-4 form (radix-4 table and kernels)
     std::shared_ptr<dsfft::DeviceTable> table;
     const dsfft::KernelCfg* k1 = nullptr;   // single kernel, or the column kernel
     const dsfft::KernelCfg* k1_plain = nullptr;  // k1's size without 16-byte staging
@@ -47,7 +52,7 @@ struct fft_plan {
 
 namespace dsfft {
 fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants,
-                      bool inverse = false);
+                      bool inverse = false, int radix = 2);
 bool tuned_choice(int dtype, int log_n, int* variants);
 int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
 // Argument checks of an execute (null, alignment, partial overlap).

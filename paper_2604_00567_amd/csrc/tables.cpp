@@ -114,6 +114,131 @@ std::vector<uint8_t> build_level_table(int64_t ncap, int dtype, int kind, bool i
     return img;
 }
 
+Radix4Entry radix4_entry(int64_t j, int64_t L, int kind, bool inverse) {
+    Radix4Entry e;
+    for (int p = 0; p < 3; ++p) e.w[p] = twiddle64((p + 1) * j, L, kind, inverse);
+    const double m1 = e.w[0].mult, m3 = e.w[2].mult;
+    e.sel = std::fabs(m1) >= std::fabs(m3);
+    e.rho = e.sel ? m3 / m1 : m1 / m3;
+    return e;
+}
+
+size_t entry4_bytes(int dtype) { return dtype == DT_F16 ? 32 : 64; }
+
+static inline uint32_t pack_h2(uint16_t lo, uint16_t hi) { return (uint32_t)lo | ((uint32_t)hi << 16); }
+static inline uint16_t neg16(uint16_t h) { return (uint16_t)(h ^ 0x8000u); }
+
+// One radix-4 device entry.  Signs: sigma = -1 on the sine path; sigma_M is
+// the outer multiplier's; sg = +1 when the outer multiplier is m(W^j).  The
+// inverse stores the last multiplier pair negated (Y1 and Y3 trade places).
+static void pack_entry4(const Radix4Entry& e, int dtype, bool inverse, uint8_t* dst) {
+    const bool s1 = e.w[0].sine, s2 = e.w[1].sine, s3 = e.w[2].sine;
+    const bool sM = e.sel ? s1 : s3;
+    const bool flip13 = s1 != s3;          // sigma1 sigma3 = -1
+    const bool neg_mm1 = (!e.sel) != inverse;
+    const double M64 = e.sel ? e.w[0].mult : e.w[2].mult;
+    if (dtype == DT_F16) {
+        uint32_t wd[8];
+        for (int p = 0; p < 3; ++p)
+            wd[p] = (e.w[p].sine ? 16u : 0u) | ((uint32_t)f64_to_f16(e.w[p].ratio) << 16);
+        const uint16_t m2 = f64_to_f16(e.w[1].mult);
+        wd[3] = pack_h2(s2 ? neg16(m2) : m2, m2);
+        const uint16_t rho = f64_to_f16(e.rho);
+        wd[4] = pack_h2(flip13 ? neg16(rho) : rho, rho);
+        const uint16_t M = f64_to_f16(M64);
+        const uint16_t sm = sM ? neg16(M) : M;      // sigma_M M
+        wd[5] = pack_h2(sm, M);
+        // (sg M, -sg sigma_M M), negated for the inverse
+        uint16_t a = M, b = neg16(sm);
+        if (neg_mm1) {
+            a = neg16(a);
+            b = neg16(b);
+        }
+        wd[6] = pack_h2(a, b);
+        wd[7] = e.sel ? 0xFFFFFFFFu : 0u;
+        std::memcpy(dst, wd, sizeof wd);
+    } else {
+        float f[16];
+        uint32_t u[16];
+        for (int p = 0; p < 3; ++p) {
+            f[p] = (float)e.w[p].ratio;
+            u[3 + p] = e.w[p].sine ? 0xFFFFFFFFu : 0u;
+        }
+        const float m2 = (float)e.w[1].mult;
+        f[6] = s2 ? -m2 : m2;
+        f[7] = m2;
+        const float rho = (float)e.rho;
+        f[8] = flip13 ? -rho : rho;
+        f[9] = rho;
+        const float M = (float)M64;
+        const float sm = sM ? -M : M;
+        f[10] = sm;
+        f[11] = M;
+        f[12] = neg_mm1 ? -M : M;
+        f[13] = neg_mm1 ? sm : -sm;
+        for (int i = 0; i < 3; ++i) std::memcpy(&u[i], &f[i], 4);
+        for (int i = 6; i < 14; ++i) std::memcpy(&u[i], &f[i], 4);
+        u[14] = e.sel ? 0xFFFFFFFFu : 0u;
+        u[15] = 0;
+        std::memcpy(dst, u, sizeof u);
+    }
+}
+
+// Entry 0: the radix-2 butterfly of W^0 (span 2) in the fields the radix-2
+// stage reads (ts1 and w2 / t1, mask1, sm2 and m2).
+static void pack_w0_entry4(const Twiddle64& t, int dtype, uint8_t* dst) {
+    uint8_t r2[16];
+    pack_entry(t, dtype, r2);
+    if (dtype == DT_F16) {
+        std::memcpy(dst + 0, r2 + 4, 4);    // ts1 <- ts
+        std::memcpy(dst + 12, r2 + 0, 4);   // w2 <- w
+    } else {
+        std::memcpy(dst + 24, r2 + 0, 8);   // (sm2, m2) <- (sm, m)
+        std::memcpy(dst + 0, r2 + 8, 4);    // t1 <- t
+        std::memcpy(dst + 12, r2 + 12, 4);  // mask1 <- mask
+    }
+}
+
+std::vector<uint8_t> build_level_table4(int64_t ncap, int dtype, int kind, bool inverse) {
+    const size_t eb = entry4_bytes(dtype);
+    // ncap entries, the upper half unused: a radix-R pass of span L0 R reads
+    // entries below L0 R / 2, and LDS copies of a pass's run [L0, L0 R) stay
+    // inside the image
+    std::vector<uint8_t> img((size_t)ncap * eb, 0);
+    pack_w0_entry4(twiddle64(0, 2, kind, inverse), dtype, img.data());
+    for (int64_t L = 4; L <= ncap; L <<= 1)
+        for (int64_t j = 0; j < L / 4; ++j)
+            pack_entry4(radix4_entry(j, L, kind, inverse), dtype, inverse,
+                        img.data() + (size_t)(L / 4 + j) * eb);
+    return img;
+}
+
+static void store_rounded(int dtype, double v, void* out, int64_t i) {
+    if (!out) return;
+    if (dtype == DT_F16) {
+        const uint16_t h = f64_to_f16(v);
+        std::memcpy((uint8_t*)out + 2 * i, &h, 2);
+    } else {
+        const uint32_t u = f32_bits((float)v);
+        std::memcpy((uint8_t*)out + 4 * i, &u, 4);
+    }
+}
+
+void build_flat_table4(int64_t n, int dtype, int kind, bool inverse, void* mult, void* ratio,
+                       uint8_t* path, void* rho, uint8_t* sel) {
+    for (int64_t k = 0; k < 3 * n / 4; ++k) {
+        const Twiddle64 t = twiddle64(k, n, kind, inverse);
+        store_rounded(dtype, t.mult, mult, k);
+        store_rounded(dtype, t.ratio, ratio, k);
+        if (path) path[k] = t.sine ? 1 : 0;
+    }
+    for (int64_t j = 0; j < n / 4; ++j) {
+        const Radix4Entry e = radix4_entry(j, n, kind, inverse);
+        store_rounded(dtype, e.rho, rho, j);
+        if (sel) sel[j] = e.sel ? 1 : 0;
+    }
+}
+
 void build_flat_table(int64_t n, int dtype, int kind, bool inverse, void* mult, void* ratio,
                       uint8_t* path) {
     for (int64_t k = 0; k < n / 2; ++k) {

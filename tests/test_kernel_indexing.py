@@ -546,9 +546,18 @@ def compiled(c, dtype):
     """The registry's rule (cfg_fits) for an entry and a plan precision."""
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = c
     esize, twsize = (4, 8) if dtype == "f16" else (8, 16)
+    if enc == "ENC_RADIX4":
+        # the radix-4 form: stored as computed, whole transforms, no lane tail,
+        # no second register set or prefetch, passes on radix-4 stage boundaries;
+        # its table entries are 32 / 64 bytes
+        if dtype == "f16f32" or mode != 0 or lane or pipe in (1, 2, 5):
+            return False
+        if lr0 % 2 != log_nu % 2 or lr1 % 2 or lr2 % 2:
+            return False
+        twsize *= 4
     if dtype == "f16f32" and (stg or pipe == 1):
         return False
-    if enc != "ENC_TABLE" and (dtype != "f16" or pipe == 1 or lane):
+    if enc not in ("ENC_TABLE", "ENC_RADIX4") and (dtype != "f16" or pipe == 1 or lane):
         return False
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     if pipe in (3, 4, 5) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0 \
@@ -572,8 +581,10 @@ def test_compiled_configurations_match_the_model(dtype):
     full = load_full_configs()
     for m in range(1, 21):
         single, cols, rows = binding.fft_config_count(1 << m, dtype)
-        want = sum(1 for c in full if c[0] == 0 and c[1] == m and compiled(c, dtype))
+        want = sum(1 for c in full if c[0] == 0 and c[1] == m and c[11] != "ENC_RADIX4" and compiled(c, dtype))
         assert single == want, (m, dtype)
+        want4 = sum(1 for c in full if c[0] == 0 and c[1] == m and c[11] == "ENC_RADIX4" and compiled(c, dtype))
+        assert binding.fft_config_count_radix4(1 << m, dtype) == want4, (m, dtype)
         lc, lr = two_pass_split(m, dtype)
         assert cols == sum(1 for c in full if c[0] == 1 and c[1] == lc and compiled(c, dtype)), (m, dtype)
         assert rows == sum(1 for c in full if c[0] == 2 and c[1] == lr and compiled(c, dtype)), (m, dtype)
@@ -621,6 +632,8 @@ def test_lds_twiddle_copy(cfg, esize, twsize):
     after the exchange area; every lane's read in each served pass lands on
     the entry the table path reads (q + L0 c), inside the copy."""
     mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
+    if enc == "ENC_RADIX4":
+        twsize *= 4                               # radix-4 entries: 32 / 64 bytes
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
     te = lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe)
     last = lds_twiddle_last_pass(pp, log_nu, log_e, mode, lane, pipe)
@@ -650,3 +663,47 @@ def test_lds_twiddle_copy(cfg, esize, twsize):
                 for c in range(1, R):
                     idx = q + L0 * c - L01
                     assert 0 <= idx < te and L01 + idx == q + L0 * c
+
+
+@pytest.mark.parametrize("cfg", [c for c in load_full_configs() if c[11] == "ENC_RADIX4"])
+def test_radix4_entry_indices(cfg):
+    """Radix-4 form: in pass P (span L0 before it, radix R) a lane's group in
+    column q reads entries q + L0 c.  The stages of the pass read c = S + e
+    (S columns done before the stage, e < S), which is entry L/4 + j of the
+    radix-4 table for the stage's span L = 4 L0 S and column j = q + L0 e; the
+    span-2 stage of an odd log2 N (first pass) reads entry 0.  Every index read
+    lies below L0 R / 2 <= N/2, inside the table (N_cap entries), and the
+    stages cover every (span, column) of the canonical radix-4 order once."""
+    mode, log_nu, log_e, upw, lr0, lr1, lr2, stg, lane, pipe, upl, enc = cfg
+    assert mode == 0 and lane == 0 and pipe not in (1, 2, 5)
+    pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    n = 1 << log_nu
+    odd = log_nu % 2
+    assert pp.lr(0) % 2 == odd and all(pp.lr(p) % 2 == 0 for p in range(1, pp.np))
+    seen = set()
+    for p in range(pp.np):
+        L0, R = 1 << pp.log_l0(p), 1 << pp.lr(p)
+        for q in range(L0):
+            S = 1
+            if p == 0 and odd:
+                assert q == 0
+                seen.add((2, 0))
+                S = 2
+            while S < R:
+                for e in range(S):
+                    c = S + e
+                    assert (1 if not (p == 0 and odd) else 2) <= c < R // 2 or (R == 4 and c == 1)
+                    idx = q + L0 * c
+                    span, j = 4 * L0 * S, q + L0 * e
+                    assert idx == span // 4 + j and j < span // 4
+                    assert idx < max(L0 * R // 2, 2) <= max(n // 2, 2)
+                    seen.add((span, j))
+                S *= 4
+    # the canonical radix-4 order: span 2 first when log2 N is odd, then every
+    # radix-4 span up to N, each with its L/4 columns
+    want = {(2, 0)} if odd else set()
+    span = 8 if odd else 4
+    while span <= n:
+        want |= {(span, j) for j in range(span // 4)}
+        span *= 4
+    assert seen == want

@@ -107,3 +107,44 @@ def test_mixed_precision_configurations():
         assert 0 < s <= s16 if m <= 14 else s == 0
         assert (c > 0 and r > 0) if m >= 12 else True
         assert c <= c16 and r <= r16
+
+
+def _round(x, dtype):
+    return oracle.rn16(x) if dtype == "f16" else np.asarray(x, np.float64).astype(np.float32)
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+@pytest.mark.parametrize("kind", ["dual_select", "linzer_feig", "cosine", "lf_w0_exempt"])
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_host_radix4_tables_match_oracle(dtype, kind, direction):
+    # the radix-4 form reads W^k for k < 3n/4 and, per column, the outer
+    # multiplier's choice and rho (computed in FP64, rounded once)
+    view = np.uint16 if dtype == "f16" else np.uint32
+    inv = direction == "inverse"
+    for m in (2, 3, 4, 7, 10, 13, 16, 20):
+        n = 1 << m
+        m_lib, r_lib, p_lib, rho_lib, sel_lib = binding.fft_table_build_radix4(n, dtype, kind, direction)
+        m64, r64, p_orc = oracle.table_count(n, 3 * n // 4, kind, inv)
+        rho64, sel_orc = oracle.pairs4(n, kind, inv)
+        assert np.array_equal(m_lib.view(view), _round(m64, dtype).view(view)), n
+        assert np.array_equal(r_lib.view(view), _round(r64, dtype).view(view)), n
+        assert np.array_equal(p_lib, p_orc.astype(np.uint8)), n
+        assert np.array_equal(rho_lib.view(view), _round(rho64, dtype).view(view)), n
+        assert np.array_equal(sel_lib, sel_orc.astype(np.uint8)), n
+
+
+def test_radix4_plan_validation_without_gpu():
+    # configurations exist for n = 2 .. 2^13 in both storage precisions, none for
+    # binary16 storage with binary32 butterflies
+    for m in range(1, 14):
+        assert binding.fft_config_count_radix4(1 << m, "f16") >= 1
+        assert binding.fft_config_count_radix4(1 << m, "f32") >= 1
+    assert binding.fft_config_count_radix4(1 << 14, "f16") == 0
+    assert binding.fft_config_count_radix4(1024, "f16f32") == 0
+    with pytest.raises(binding.FFTError):
+        binding.fft_table_build_radix4(2, "f16", "dual_select")
+    with pytest.raises(binding.FFTError):
+        binding.fft_plan_create_radix4(1024, 1, "f16", "dual_select", 0)
+    assert "direction" in binding.fft_last_error()
+    with pytest.raises(binding.FFTError):
+        binding.fft_plan_create_radix4(1024, 1, "f16f32", "dual_select")
