@@ -4,6 +4,10 @@
     python -m paper_2604_00567_amd.profile_targets large      # N = 2^15..2^20
     python -m paper_2604_00567_amd.profile_targets batch      # uneven batch
     python -m paper_2604_00567_amd.profile_targets fixed N BATCH DTYPE
+
+Every run starts with three plain 256 MiB device-to-device copies, the
+calibration for counter passes (what FETCH_SIZE / WRITE_SIZE read for a copy
+of known size).
 """
 from __future__ import annotations
 
@@ -49,8 +53,19 @@ def batch() -> None:
     b.close()
 
 
+def calibrate(copies: int = 3, nbytes: int = 256 << 20) -> None:
+    """Plain device-to-device copies of `nbytes` (runtime copy kernels)."""
+    a = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(copies):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
 def main(argv) -> int:
     torch.cuda.set_stream(torch.cuda.Stream())
+    calibrate()
     if argv[:1] == ["large"]:
         large()
     elif argv[:1] == ["batch"]:
