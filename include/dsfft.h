@@ -138,11 +138,12 @@ int fft_execute(fft_plan* plan, const void* in, void* out, void* stream);
  */
 int fft_execute_scratch(fft_plan* plan, const void* in, void* out, void* stream);
 
-/* Frees the plan.  A two-pass plan first waits for its last execution (its
- * workspace may still be in use); a single-pass plan holds no device memory
- * that its launches read or write (twiddle tables are shared and live until
- * the process ends), so it returns at once and launches already enqueued
- * complete normally.  NULL-safe. */
+/* Frees the plan.  A two-pass plan that owns its workspace first waits until
+ * the device has finished all work enqueued so far (its launches may still use
+ * the workspace); other plans hold no device memory that their launches read
+ * or write (twiddle tables are shared and live until the process ends), so
+ * they return at once and launches already enqueued complete normally.
+ * NULL-safe. */
 void fft_destroy(fft_plan* plan);
 
 /*
@@ -183,7 +184,9 @@ int fft_plan_workspace_bytes(const fft_plan* plan, size_t* bytes);
 /*
  * Replaces the plan-owned workspace by caller memory (device pointer of at
  * least fft_plan_workspace_bytes bytes, 16-byte aligned), e.g. from torch's
- * allocator.  The caller keeps it alive while the plan may run.
+ * allocator; the plan's own workspace is freed once the device has finished
+ * the work enqueued so far.  The caller keeps its memory alive while the plan
+ * may run.
  */
 int fft_plan_set_workspace(fft_plan* plan, void* dev_ptr, size_t bytes);
 
@@ -303,7 +306,8 @@ int fft_batch_elements(const fft_batch* batch, int64_t* elements);
  * workspace bytes of the batch. */
 int fft_batch_info(const fft_batch* batch, int64_t* items, int64_t* grid, size_t* workspace_bytes);
 
-/* Waits for the batch's last execution, then frees it.  NULL-safe. */
+/* Waits until the device has finished the work enqueued so far (the batch's
+ * launches included), then frees it.  NULL-safe. */
 void fft_batch_destroy(fft_batch* batch);
 
 /* The work list an uneven batch of sizes n[0..count) and `dtype` would run
@@ -353,6 +357,77 @@ int fft_serve_slot_query(fft_serve_slot* slot);
 
 /* Waits for the slot's last launch, then frees it.  NULL-safe. */
 void fft_serve_slot_destroy(fft_serve_slot* slot);
+
+/*
+ * Native serving loops (the continuous-batching server and its comparison)
+ * over an arrival trace.  Requests r < count arrive at t[r] seconds (non-
+ * decreasing, from the loop's start) and ask for batch[r] transforms of n[r]
+ * points (powers of two, 2 .. 2^18) in dtype[r] (FFT_F16 or FFT_F32); their
+ * data are generated on the device (fft_serve_fill, keyed by the seed and the
+ * request's position among the requests of its precision, in arrival order),
+ * transformed forward with the `kind` table and, when out_dev is not NULL,
+ * copied to out_dev + out_off[r] bytes (for checks).  done_t[r] receives the
+ * host time, in seconds from the loop's start, at which the request's
+ * completion was observed.
+ *   FFT_SERVE_CONTINUOUS  `slots` in-flight steps on as many streams.  Each
+ *       turn retires finished steps, then admits waiting requests in arrival
+ *       order into every free slot while each fits the HBM budget (request bytes
+ *       in and out, plus workspace for split transforms, on top of the bytes in
+ *       flight) and the slot's capacities (slot_bytes of data per precision,
+ *       max_transforms whole transforms, max_large split ones, max_items work
+ *       items, max_step_requests requests), generates the step's data and runs
+ *       one step per precision: the serving-slot kernels (fft_serve_slot_launch),
+ *       or for a step of at most direct_max whole-size requests one cached-plan
+ *       launch per request.  Steps on different slots overlap on the device.
+ *   FFT_SERVE_PER_REQUEST one cached plan (per shape and stream) and one launch
+ *       per request, round-robin over `slots` streams, admitted in arrival
+ *       order under the same budget (request data in a ring of
+ *       max(slot_bytes, largest request) bytes per stream).
+ * Returns FFT_OK, FFT_EINVAL (bad arguments, or a request that can never be
+ * admitted), FFT_ENOMEM or FFT_EHIP; stats (may be NULL) receives the steps,
+ * direct steps, mean requests per step, peak bytes in flight, peak concurrent
+ * steps and the wall time from the first arrival to the last completion.
+ */
+enum { FFT_SERVE_CONTINUOUS = 0, FFT_SERVE_PER_REQUEST = 1 };
+typedef struct {
+    int mode;                  /* FFT_SERVE_CONTINUOUS or FFT_SERVE_PER_REQUEST */
+    int slots;                 /* in-flight steps (continuous) or streams (per request), 1 .. 64 */
+    int kind;                  /* fft_table_kind */
+    int direct_max;            /* continuous: plan-launched steps of at most this many requests */
+    int max_step_requests;
+    int max_large;             /* split transforms per step and precision */
+    int64_t max_transforms;    /* whole transforms per step and precision */
+    int64_t max_items;         /* work items per step and precision */
+    size_t budget_bytes;       /* HBM admission budget */
+    size_t slot_bytes;         /* data bytes per slot and precision (continuous); ring size (per request) */
+    uint64_t seed;             /* payload generator key */
+} fft_serve_config;
+typedef struct {
+    int64_t steps, direct_steps;
+    double mean_requests_per_step;
+    uint64_t max_inflight_bytes;
+    int max_concurrent;
+    double wall_s;
+} fft_serve_stats;
+int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n, const int64_t* batch,
+                  const int32_t* dtype, int64_t count, double* done_t, fft_serve_stats* stats,
+                  void* out_dev, const int64_t* out_off);
+
+/* The payload generator of the serving loops: complex elements first ..
+ * first + elems - 1 of precision `dtype`'s stream, written to `data` (device,
+ * interleaved re/im): each is one Box-Muller pair of N(0, 1) values from a
+ * Philox4x32-10 draw keyed by `seed` and the element's index, rounded once to
+ * the precision.  Enqueued on `stream`. */
+int fft_serve_fill(fft_dtype dtype, void* data, int64_t elems, uint64_t first, uint64_t seed, void* stream);
+
+/* Host only: the requests the continuous loop would admit into one step, from
+ * position `head` of a trace whose requests have all arrived, with
+ * inflight_bytes already in flight (the rule of FFT_SERVE_CONTINUOUS above).
+ * taken receives up to cfg->max_step_requests request indices, *ntaken their
+ * number, *inflight_out the bytes in flight after them. */
+int fft_serve_admit(const int64_t* n, const int64_t* batch, const int32_t* dtype, int64_t count,
+                    int64_t head, size_t inflight_bytes, const fft_serve_config* cfg, int64_t* taken,
+                    int64_t* ntaken, size_t* inflight_out);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,24 @@ import torch  # noqa: E402,F401
 
 _lib = ctypes.CDLL(LIB_PATH)
 _vp, _i64, _int, _sz = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_size_t
+
+FFT_SERVE_CONTINUOUS, FFT_SERVE_PER_REQUEST = 0, 1
+
+
+class ServeConfig(ctypes.Structure):
+    """fft_serve_config."""
+    _fields_ = [("mode", ctypes.c_int), ("slots", ctypes.c_int), ("kind", ctypes.c_int),
+                ("direct_max", ctypes.c_int), ("max_step_requests", ctypes.c_int),
+                ("max_large", ctypes.c_int), ("max_transforms", ctypes.c_int64),
+                ("max_items", ctypes.c_int64), ("budget_bytes", ctypes.c_size_t),
+                ("slot_bytes", ctypes.c_size_t), ("seed", ctypes.c_uint64)]
+
+
+class ServeStats(ctypes.Structure):
+    """fft_serve_stats."""
+    _fields_ = [("steps", ctypes.c_int64), ("direct_steps", ctypes.c_int64),
+                ("mean_requests_per_step", ctypes.c_double), ("max_inflight_bytes", ctypes.c_uint64),
+                ("max_concurrent", ctypes.c_int), ("wall_s", ctypes.c_double)]
 _SIGS = {
     "fft_last_error": ([], ctypes.c_char_p),
     "fft_plan_create": ([_i64, _i64, _int, _int], _vp),
@@ -78,6 +96,11 @@ _SIGS = {
     "fft_serve_slot_launch": ([_vp, _vp, _vp, _vp, _i64, _vp, _vp], _int),
     "fft_serve_slot_query": ([_vp], _int),
     "fft_serve_slot_destroy": ([_vp], None),
+    "fft_serve_run": ([ctypes.POINTER(ServeConfig), _vp, _vp, _vp, _vp, _i64, _vp, ctypes.POINTER(ServeStats),
+                       _vp, _vp], _int),
+    "fft_serve_fill": ([_int, _vp, _i64, ctypes.c_uint64, ctypes.c_uint64, _vp], _int),
+    "fft_serve_admit": ([_vp, _vp, _vp, _i64, _i64, _sz, ctypes.POINTER(ServeConfig), _vp,
+                         ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
 }
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -428,3 +451,38 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _trace_arrays(trace):
+    t = np.ascontiguousarray(trace["t"], dtype=np.float64)
+    n = np.ascontiguousarray(trace["n"], dtype=np.int64)
+    b = np.ascontiguousarray(trace["batch"], dtype=np.int64)
+    d = np.ascontiguousarray([_dt(str(x)) for x in trace["dtype"]], dtype=np.int32)
+    return t, n, b, d
+
+
+def fft_serve_run(cfg: ServeConfig, trace, out_dev: int = 0, out_off=None):
+    """Runs the native serving loop over `trace` (dict of t, n, batch, dtype);
+    returns (done_t seconds per request, ServeStats)."""
+    t, n, b, d = _trace_arrays(trace)
+    done = np.empty(t.size, np.float64)
+    st = ServeStats()
+    off = None if out_off is None else np.ascontiguousarray(out_off, dtype=np.int64)
+    _check(_lib.fft_serve_run(ctypes.byref(cfg), t.ctypes.data, n.ctypes.data, b.ctypes.data, d.ctypes.data,
+                              t.size, done.ctypes.data, ctypes.byref(st), out_dev or None,
+                              None if off is None else off.ctypes.data))
+    return done, st
+
+
+def fft_serve_fill(dtype, data_ptr: int, elems: int, first: int, seed: int, stream: int = 0) -> None:
+    _check(_lib.fft_serve_fill(_dt(dtype), data_ptr, elems, first, seed, stream))
+
+
+def fft_serve_admit(trace, head: int, inflight_bytes: int, cfg: ServeConfig):
+    """Host-only admission of one continuous step: (taken indices, bytes in flight)."""
+    _, n, b, d = _trace_arrays(dict(trace, t=np.zeros(len(trace["n"]))))
+    taken = np.empty(max(1, cfg.max_step_requests), np.int64)
+    nt, infl = _i64(), _sz()
+    _check(_lib.fft_serve_admit(n.ctypes.data, b.ctypes.data, d.ctypes.data, n.size, head, inflight_bytes,
+                                ctypes.byref(cfg), taken.ctypes.data, ctypes.byref(nt), ctypes.byref(infl)))
+    return taken[:nt.value].tolist(), infl.value

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdsfft.so")
 
-HIP_SOURCES = ["api.cpp", "batch.cpp", "serve.cpp", "tune.cpp", "scratch.cpp", "kernels_f16.hip", "kernels_f32.hip",
+HIP_SOURCES = ["api.cpp", "batch.cpp", "serve.cpp", "serve_loop.cpp", "tune.cpp", "scratch.cpp", "kernels_f16.hip", "kernels_f32.hip",
                "kernels_f16f32.hip", "kernels_batch.hip"]
 CXX_SOURCES = ["tables.cpp"]
 

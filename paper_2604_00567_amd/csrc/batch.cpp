@@ -59,15 +59,17 @@ struct fft_batch {
     hipGraphNode_t lnode[dsfft::kNumLists] = {};   // list kernels (binary16 2^16, 2^15)
     const void* cap_in = nullptr;
     void* cap_out = nullptr;
-    hipEvent_t last = nullptr;
     ~fft_batch();
 };
 
+// The batch's launches may still use its buffers: free them once the device
+// has finished the work enqueued so far (an event per execute would cost
+// device time on every replay).
 fft_batch::~fft_batch() {
-    if (last) {
-        (void)hipEventSynchronize(last);
-        (void)hipEventDestroy(last);
-    }
+    int cur = 0;
+    const bool have_cur = hipGetDevice(&cur) == hipSuccess;
+    if (have_cur && cur != device) (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (d_items) (void)hipFree(d_items);
@@ -75,6 +77,7 @@ fft_batch::~fft_batch() {
     if (d_lists) (void)hipFree(d_lists);
     if (d_ctl) (void)hipFree(d_ctl);
     if (ws) (void)hipFree(ws);
+    if (have_cur && cur != device) (void)hipSetDevice(cur);
 }
 
 namespace dsfft {
@@ -371,7 +374,6 @@ int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s) {
     if (rc != FFT_OK) return rc;
     hipError_t e = hipGraphLaunch(b->exec, s);
     if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
-    if ((e = hipEventRecord(b->last, s)) != hipSuccess) return hip_error(e, "hipEventRecord");
     return FFT_OK;
 }
 
@@ -417,10 +419,6 @@ fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, co
     if (get_table(nmax, dtype, kind, false, &b->table) != FFT_OK) return nullptr;
     if (build_items(b.get()) != FFT_OK) return nullptr;
     if (upload(b.get()) != FFT_OK) return nullptr;
-    if ((e = hipEventCreateWithFlags(&b->last, hipEventDisableTiming)) != hipSuccess) {
-        hip_error(e, "hipEventCreate");
-        return nullptr;
-    }
     return b.release();
 }
 

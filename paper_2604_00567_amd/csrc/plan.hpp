@@ -46,15 +46,20 @@ struct fft_plan {
     size_t ws_need = 0, ws_bytes = 0;
     void* ws = nullptr;
     bool ws_owned = false;
-    hipEvent_t last = nullptr;
     ~fft_plan();
 };
 
 namespace dsfft {
+// alloc_ws = false: a two-pass plan gets no workspace of its own (the caller
+// sets one before the first execute).
 fft_plan* plan_create(int64_t n, int64_t batch, int dtype, int kind, const int* variants,
-                      bool inverse = false, int radix = 2);
+                      bool inverse = false, int radix = 2, bool alloc_ws = true);
+// Largest workspace a two-pass plan asks for (its chunk cap).
+constexpr size_t kMaxWorkspaceBytes = (size_t)128 << 20;
 bool tuned_choice(int dtype, int log_n, int* variants);
 int plan_execute(fft_plan* p, const void* in, void* out, hipStream_t s);
+// Frees a plan-owned workspace after the plan's device is idle.
+void release_workspace(fft_plan* p);
 // Argument checks of an execute (null, alignment, partial overlap).
 int check_execute_args(const fft_plan* p, const void* in, const void* out);
 // The plan's launches with its two-pass intermediate in ws, chunk transforms at a time.

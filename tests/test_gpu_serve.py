@@ -64,8 +64,10 @@ def test_results_alone_equal_results_in_mix():
 
 def test_small_steps_run_through_plans_with_the_same_results():
     """At a low arrival rate most steps hold one or two requests and take the
-    direct form (one plan launch per request); their results equal the
-    batch-kernel form's and the oracle's."""
+    direct form (one plan launch per request); a request's data depend only on
+    its position in the trace, so the direct form, the batch-kernel form and
+    one launch per request give the same outputs bit for bit, and they equal
+    the oracle's."""
     import torch
     tr = small_trace(120, 24, rate=4000.0, log_hi=16)
     outs = {}
@@ -75,30 +77,56 @@ def test_small_steps_run_through_plans_with_the_same_results():
             stats = srv.run(tr)
             torch.cuda.synchronize()
         finally:
+            ins, res = dict(srv.inputs), dict(srv.outputs)
             srv.close()
         assert stats["requests"] == tr["t"].size
         if direct_max:
             assert stats["direct_steps"] > 0
         else:
             assert stats["direct_steps"] == 0
-        outs[direct_max] = (dict(srv.inputs), dict(srv.outputs))
-    # the generator is seeded and advances per step, so inputs can differ
-    # between the runs: compare each run's outputs with a plan on its inputs
-    for direct_max, (ins, res) in outs.items():
-        for rid in range(0, tr["t"].size, 7):
-            n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
-            x = ins[rid].reshape(b, n, 2)
-            y_alone = torch.empty_like(x)
-            p = binding.Plan(n, b, dt, "dual_select")
-            p.execute(x, y_alone)
-            torch.cuda.synchronize()
-            p.close()
-            assert mismatches(res[rid].reshape(b, n, 2).cpu().numpy(), y_alone.cpu().numpy()) == 0
+        outs[direct_max] = (ins, res)
+    io = {}
+    run_per_request(tr, streams=2, seed=7, keep_io=io)
+    torch.cuda.synchronize()
+    for rid in range(tr["t"].size):
+        a = outs[2][1][rid].cpu().numpy()
+        assert mismatches(a, outs[0][1][rid].cpu().numpy()) == 0, rid
+        assert mismatches(a, io[rid][1].cpu().numpy()) == 0, rid
+        assert mismatches(outs[2][0][rid].cpu().numpy(), io[rid][0].cpu().numpy()) == 0, rid
     ins, res = outs[2]
+    for rid in range(0, tr["t"].size, 7):
+        n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
+        y_alone = plan_alone(ins[rid], n, b, dt)
+        assert mismatches(res[rid].cpu().numpy(), y_alone.cpu().numpy()) == 0
     for rid in range(0, tr["t"].size, 30):
         n, b, dt = int(tr["n"][rid]), int(tr["batch"][rid]), str(tr["dtype"][rid])
         x = ins[rid].reshape(b, n, 2).cpu().numpy()
         assert mismatches(res[rid].reshape(b, n, 2).cpu().numpy(), oracle.emulate(x, "dual_select", dt)) == 0
+
+
+def test_payload_generator():
+    """The serving payload generator: deterministic, keyed by element index (a
+    slice of a longer draw equals the draw of that slice), N(0, 1) moments,
+    different for the two precisions' streams and for another seed."""
+    import torch
+    m = 1 << 20
+    a = torch.empty(2 * m, dtype=torch.float32, device="cuda")
+    b = torch.empty(2 * 1000, dtype=torch.float32, device="cuda")
+    c = torch.empty(2 * m, dtype=torch.float32, device="cuda")
+    h = torch.empty(2 * m, dtype=torch.float16, device="cuda")
+    binding.fft_serve_fill("f32", a.data_ptr(), m, 0, 11)
+    binding.fft_serve_fill("f32", b.data_ptr(), 1000, 5000, 11)
+    binding.fft_serve_fill("f32", c.data_ptr(), m, 0, 12)
+    binding.fft_serve_fill("f16", h.data_ptr(), m, 0, 11)
+    torch.cuda.synchronize()
+    av = a.cpu().numpy()
+    assert np.array_equal(av[10000:12000], b.cpu().numpy())
+    assert abs(av.mean()) < 5e-3 and abs(av.var() - 1.0) < 5e-3
+    assert abs(np.mean(av ** 4) - 3.0) < 0.05                      # normal kurtosis
+    assert not np.array_equal(av, c.cpu().numpy())
+    hv = h.cpu().numpy().astype(np.float64)
+    assert np.isfinite(hv).all() and abs(hv.var() - 1.0) < 5e-3
+    assert np.mean(np.abs(hv - av) < 1e-2) < 0.01                  # another stream, not a rounded copy
 
 
 def test_budget_is_respected():

@@ -4,7 +4,7 @@ import numpy as np
 
 from paper_2604_00567_amd import inputs
 from paper_2604_00567_amd import binding
-from paper_2604_00567_amd.serve import ELEM_BYTES, admit_step, is_split, latency_summary, request_bytes
+from paper_2604_00567_amd.serve import ELEM_BYTES, generator_offsets, is_split, latency_summary, request_bytes
 
 
 def test_latency_summary_synthetic_clock():
@@ -20,39 +20,65 @@ def _trace(k, seed):
     return inputs.poisson_trace(20000.0, k / 20000.0, seed)
 
 
+def _cfg(budget, slot_bytes=256 << 20, max_step=64):
+    return binding.ServeConfig(mode=binding.FFT_SERVE_CONTINUOUS, slots=4, kind=0, direct_max=2,
+                               max_step_requests=max_step, max_large=1 << 12, max_transforms=1 << 15,
+                               max_items=1 << 18, budget_bytes=budget, slot_bytes=slot_bytes, seed=0)
+
+
 def test_admission_respects_budget_and_order():
+    # the library's own admission rule (the continuous loop calls the same code)
     tr = _trace(2000, 3)
     total = tr["t"].size
     nb = [request_bytes(int(n), int(b), str(d)) for n, b, d in zip(tr["n"], tr["batch"], tr["dtype"])]
-    pending = list(range(total))
     budget = 512 << 20
-
-    def fits(plan, n, b, dt):
-        return plan[dt][0] + n * b <= (256 << 20) // ELEM_BYTES[dt]
-
+    cfg = _cfg(budget)
     head, inflight, seen = 0, 0, []
     steps = 0
     while head < total:
-        take, head2, inflight2 = admit_step(pending, head, tr, inflight, budget, fits, 64, nb)
+        take, inflight2 = binding.fft_serve_admit(tr, head, inflight, cfg)
         if not take:                             # nothing fits: everything in flight completes
+            assert inflight > 0
             inflight = 0
             continue
-        assert take == pending[head:head2]       # arrival order, no skipping
+        assert take == list(range(head, head + len(take)))     # arrival order, no skipping
+        assert len(take) <= cfg.max_step_requests
         # in flight grows by the requests' bytes; each was admitted only with
-        # room for its workspace too (the slot's own arena holds it)
+        # room for its workspace too
         assert inflight2 == inflight + sum(nb[r] for r in take)
         room = inflight
+        used = {"f16": 0, "f32": 0}
         for r in take:
             n, dt = int(tr["n"][r]), str(tr["dtype"][r])
             ws = n * int(tr["batch"][r]) * ELEM_BYTES[dt] if is_split(n, dt) else 0
             assert room + nb[r] + ws <= budget
             room += nb[r]
+            used[dt] += n * int(tr["batch"][r]) * ELEM_BYTES[dt]
+        assert max(used.values()) <= cfg.slot_bytes              # the slot's arena per precision
+        # the next request did not fit (or the step was full)
+        if head + len(take) < total and len(take) < cfg.max_step_requests:
+            r = head + len(take)
+            n, dt = int(tr["n"][r]), str(tr["dtype"][r])
+            ws = n * int(tr["batch"][r]) * ELEM_BYTES[dt] if is_split(n, dt) else 0
+            over_budget = inflight2 + nb[r] + ws > budget
+            over_slot = used[dt] + n * int(tr["batch"][r]) * ELEM_BYTES[dt] > cfg.slot_bytes
+            assert over_budget or over_slot
         seen += take
-        head, inflight = head2, inflight2
+        head, inflight = head + len(take), inflight2
         steps += 1
         if steps % 3 == 0:
             inflight = 0                         # completions free the budget
     assert seen == list(range(total))
+
+
+def test_admission_whole_transform_capacity():
+    # many whole-size requests: a step stops at the slot's transform capacity
+    k = 50
+    tr = {"n": np.full(k, 256, np.int64), "batch": np.full(k, 64, np.int64), "dtype": np.array(["f16"] * k)}
+    cfg = _cfg(1 << 40)
+    cfg.max_transforms = 64 * 7 + 10
+    take, _ = binding.fft_serve_admit(tr, 0, 0, cfg)
+    assert take == list(range(7))
 
 
 def test_trace_recipe():
@@ -75,3 +101,8 @@ def test_split_rule_matches_the_library():
             _, _, _, _, ws = binding.fft_batch_work_list([n, n], dt)
             assert (ws > 0) == is_split(n, dt), (dt, m)
             assert ws == (2 * n if is_split(n, dt) else 0)
+
+
+def test_generator_offsets():
+    tr = {"n": np.array([4, 8, 16, 2]), "batch": np.array([1, 2, 1, 3]), "dtype": np.array(["f16", "f32", "f16", "f32"])}
+    assert generator_offsets(tr).tolist() == [0, 0, 4, 16]
