@@ -62,6 +62,8 @@ struct BatchGeo {
     static constexpr int kTwiddleLds = 0;
     static constexpr int kTwiddlePrefix = TPX;
     static constexpr int kEncoding = ENC_TABLE;
+    // an item's units need not be consecutive in memory
+    static constexpr bool kBlockRsrc = false;
     const int64_t* offs;
     BatchItem it;
     int lane_id;       // threadIdx.x, made opaque per configuration (batch_unit)
@@ -168,6 +170,8 @@ struct ListGeo {
     static constexpr int kTwiddleLds = 0;
     static constexpr int kTwiddlePrefix = TPX;
     static constexpr int kEncoding = ENC_TABLE;
+    // one unit per workgroup (the transform at offs[ublk])
+    static constexpr bool kBlockRsrc = true;
     const int64_t* offs;
     int64_t ublk, units;
     int lane_id;
@@ -182,8 +186,8 @@ struct ListGeo {
     }
     __device__ __forceinline__ bool active(int ul) const { return ublk + ul < units; }
     __device__ __forceinline__ int tid() const { return lane_id; }
-    __device__ __forceinline__ int64_t block_first(int) const { return 0; }
-    __device__ __forceinline__ int64_t block_units(int) const { return 0; }
+    __device__ __forceinline__ int64_t block_first(int) const { return ublk < units ? offs[ublk] : 0; }
+    __device__ __forceinline__ int64_t block_units(int) const { return ublk < units ? 1 : 0; }
 };
 
 template <class E, int LOG_NU, int LOG_E, int LR0, int LR1, int LR2, int TPX>

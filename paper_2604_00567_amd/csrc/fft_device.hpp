@@ -347,6 +347,48 @@ __device__ __forceinline__ void store_elem(E v, S* p) {
     else *p = s;
 }
 
+// Whole-transform blocks (a workgroup's units contiguous in memory) move
+// through a buffer resource over the block: each access is the lane's 32-bit
+// byte offset plus a compile-time offset held in a scalar register, so no
+// per-access 64-bit address arithmetic runs on the vector ALU (which the
+// largest transforms, at 6 FMAs per byte, cannot spare), and accesses past
+// the block's end read zero and write nothing.  Word 3 of a gfx9 buffer
+// descriptor for raw (unformatted) dword access is 0x00020000.
+typedef __amdgpu_buffer_rsrc_t rsrc_t;
+template <class S>
+__device__ __forceinline__ rsrc_t block_rsrc(const S* base, int64_t elems) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(base), 0, (int)(elems * (int64_t)sizeof(S)),
+                                             0x00020000);
+}
+// Cache policy: 2 = non-temporal (streaming), as __builtin_nontemporal_load/store.
+// A constant offset below 4096 fits the instruction's own offset field; larger
+// ones go to the scalar offset register.
+template <bool STREAM, class E, class S>
+__device__ __forceinline__ E buf_load(rsrc_t r, uint32_t lane_off, uint32_t c) {
+    const uint32_t voff = c < 4096 ? lane_off + c : lane_off;
+    const uint32_t soff = c < 4096 ? 0 : c;
+    if constexpr (sizeof(S) == 4) {
+        const uint32_t u = __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, STREAM ? 2 : 0);
+        return to_compute(__builtin_bit_cast(S, u), E{});
+    } else {
+        static_assert(sizeof(S) == 8, "binary16 or binary32 pairs");
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, STREAM ? 2 : 0);
+        return to_compute(__builtin_bit_cast(S, u), E{});
+    }
+}
+template <bool STREAM, class E, class S>
+__device__ __forceinline__ void buf_store(E v, rsrc_t r, uint32_t lane_off, uint32_t c) {
+    const uint32_t voff = c < 4096 ? lane_off + c : lane_off;
+    const uint32_t soff = c < 4096 ? 0 : c;
+    const S s = to_storage(v, S{});
+    if constexpr (sizeof(S) == 4) {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, s), r, voff, soff, STREAM ? 2 : 0);
+    } else {
+        typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, s), r, voff, soff, STREAM ? 2 : 0);
+    }
+}
+
 // Level-ordered twiddle table: entry L/2 + j is T_L[j] = W_L^j for span L (a
 // power of two) and j < L/2, stored as TwH/TwF.  Since theta = -(2 pi j)/L
 // scales exactly by powers of two, T_L[j] equals T_N[j N / L] bit for bit, so
@@ -699,6 +741,8 @@ struct GridGeoT {
     static constexpr int kTwiddlePrefix = 0;
     // the butterfly's path encoding (bfly_enc)
     static constexpr int kEncoding = ENC;
+    // a workgroup's units are consecutive in memory (block_first, block_units)
+    static constexpr bool kBlockRsrc = true;
     int64_t ublk, units;
     int log_m;
     int lane_id;       // threadIdx.x (opaque per block in the persistent loop)
@@ -740,6 +784,26 @@ __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
     const int tid = gp.tid();
     const int ul0 = unit_fast ? (tid % UPW) : (tid / G) * UPL;
     const int g = unit_fast ? (tid / UPW) : (tid % G);
+    if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc) {
+        const rsrc_t rs = block_rsrc(in + gp.block_first(LOG_NU), gp.block_units(UPW) << LOG_NU);
+#pragma unroll
+        for (int k = 0; k < UPL; ++k) {
+            E* vk = v + k * EL;
+            if (gp.active(ul0 + k)) {
+#pragma unroll
+                for (int u = 0; u < GPL; ++u) {
+                    const uint32_t lane_off = (uint32_t)(((ul0 + k) * NU + g + G * u) * (int)sizeof(SI));
+#pragma unroll
+                    for (int i = 0; i < R; ++i)
+                        vk[u * R + i] = buf_load<true, E, SI>(rs, lane_off, (uint32_t)(M * i * (int)sizeof(SI)));
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < EL; ++e) vk[e] = E{};
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < UPL; ++k) {
         E* vk = v + k * EL;
@@ -1096,6 +1160,22 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
             __syncthreads();
             stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
                                                gp.block_units(UPW) << LOG_NU);
+        } else if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc) {
+            const rsrc_t rs = block_rsrc(out + gp.block_first(LOG_NU), gp.block_units(UPW) << LOG_NU);
+#pragma unroll
+            for (int k = 0; k < UPL; ++k) {
+                if (gp.active(ul0 + k)) {
+#pragma unroll
+                    for (int u = 0; u < GPL; ++u) {
+                        const int q = g + G * u;  // M = 1: every group is a column
+                        const uint32_t lane_off = (uint32_t)(((ul0 + k) * NU + q) * (int)sizeof(SO));
+#pragma unroll
+                        for (int e = 0; e < R; ++e)
+                            buf_store<true, E, SO>(v[k * EL + u * R + e], rs, lane_off,
+                                                   (uint32_t)(L0 * e * (int)sizeof(SO)));
+                    }
+                }
+            }
         } else {
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
