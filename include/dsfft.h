@@ -289,9 +289,22 @@ fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, ff
 fft_batch* fft_batch_create_tuned(const int64_t* n, int64_t count, fft_dtype dtype,
                                   fft_table_kind kind, int choice_1024, int choice_4096);
 
-/* Tuner for the uneven batch: times the alternatives for the 2^10 and 2^12
- * size classes (class-only batches, `reps` replays, outputs required to be
- * bit-identical) and returns the faster choice of each (0 or 1). */
+/* Same, with a choice per size class: alt[m] = 1 takes the alternative
+ * configuration of the 2^m-point class (alt has 15 entries, m = 0 .. 14;
+ * classes 2^7 .. 2^12 have one: another radix split, units per workgroup and
+ * elements per lane), 0 its default; NULL takes every default. */
+fft_batch* fft_batch_create_classes(const int64_t* n, int64_t count, fft_dtype dtype,
+                                    fft_table_kind kind, const int32_t* alt);
+
+/* Tuner for the uneven batch: for each size class with an alternative
+ * configuration (2^7 .. 2^12), times a batch of that class alone with both
+ * (2^24 elements, `reps` graph replays, outputs required to be bit-identical)
+ * and sets alt_out[m] (15 entries) to 1 where the alternative is faster, for
+ * fft_batch_create_classes. */
+int fft_batch_tune_classes(fft_dtype dtype, fft_table_kind kind, int reps, int32_t* alt_out);
+
+/* The 2^10 and 2^12 choices of fft_batch_tune_classes (0 or 1 each), for
+ * fft_batch_create_tuned. */
 int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1024,
                    int* choice_4096);
 
@@ -377,8 +390,8 @@ void fft_serve_slot_destroy(fft_serve_slot* slot);
  *       max_transforms whole transforms, max_large split ones, max_items work
  *       items, max_step_requests requests), generates the step's data and runs
  *       one step per precision: the serving-slot kernels (fft_serve_slot_launch),
- *       or for a step of at most direct_max whole-size requests one cached-plan
- *       launch per request.  Steps on different slots overlap on the device.
+ *       or for a step of at most direct_max requests one cached-plan launch per
+ *       request (two-pass plans on a workspace of the slot).  Steps on different slots overlap on the device.
  *   FFT_SERVE_PER_REQUEST one cached plan (per shape and stream) and one launch
  *       per request, round-robin over `slots` streams, admitted in arrival
  *       order under the same budget (request data in a ring of

@@ -81,6 +81,8 @@ _SIGS = {
                           ctypes.POINTER(_int)], _int),
     "fft_batch_create": ([_vp, _i64, _int, _int], _vp),
     "fft_batch_create_tuned": ([_vp, _i64, _int, _int, _int, _int], _vp),
+    "fft_batch_create_classes": ([_vp, _i64, _int, _int, _vp], _vp),
+    "fft_batch_tune_classes": ([_int, _int, _int, _vp], _int),
     "fft_batch_execute": ([_vp, _vp, _vp, _vp], _int),
     "fft_batch_elements": ([_vp, ctypes.POINTER(_i64)], _int),
     "fft_batch_info": ([_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64), ctypes.POINTER(_sz)], _int),
@@ -268,10 +270,21 @@ def fft_batch_tune(dtype, kind="dual_select", reps: int = 5) -> tuple[int, int]:
     return a.value, b.value
 
 
+def fft_batch_tune_classes(dtype, kind="dual_select", reps: int = 5) -> list[int]:
+    """Per log2 N (0..14): 1 where the batch tuner picked the alternative configuration."""
+    alt = np.zeros(15, np.int32)
+    _check(_lib.fft_batch_tune_classes(_dt(dtype), _kd(kind), reps, alt.ctypes.data))
+    return alt.tolist()
+
+
 def fft_batch_create(sizes, dtype, kind, choice=None) -> int:
+    """choice: None (defaults), (choice_1024, choice_4096), or 15 per-class flags."""
     arr = np.ascontiguousarray(np.asarray(sizes, dtype=np.int64))
     if choice is None:
         h = _lib.fft_batch_create(arr.ctypes.data, arr.size, _dt(dtype), _kd(kind))
+    elif len(choice) == 15:
+        alt = np.ascontiguousarray(np.asarray(choice, dtype=np.int32))
+        h = _lib.fft_batch_create_classes(arr.ctypes.data, arr.size, _dt(dtype), _kd(kind), alt.ctypes.data)
     else:
         h = _lib.fft_batch_create_tuned(arr.ctypes.data, arr.size, _dt(dtype), _kd(kind),
                                         int(choice[0]), int(choice[1]))

@@ -19,16 +19,18 @@ namespace dsfft {
 const int kSmallCfg[kMaxSingleLog + 1] = {-1, HB_N2, HB_N4, HB_N8, HB_N16, HB_N32, HB_N64, HB_N128,
                                           HB_N256, HB_N512, HB_N1024, HB_N2048, HB_N4096, HB_N8192,
                                           HB_N16384};
+const int kAltCfg[kMaxSingleLog + 1] = {-1, -1, -1, -1, -1, -1, -1, HB_N128_B, HB_N256_B, HB_N512_B,
+                                        HB_N1024_B, HB_N2048_B, HB_N4096_B, -1, -1};
 int cfg_upw(int cfg) {
     switch (cfg) {
         case HB_N2: case HB_N4: case HB_N8: return 512;
         case HB_N16: case HB_N32: return 128;
         case HB_N64: case HB_N128: case HB_ROWS128: case HB_COLS256:
         case HB_ROWS256: return 64;
-        case HB_N256: case HB_N512: case HB_COLS512: case HB_ROWS512: return 32;
-        case HB_N1024: return 16;
+        case HB_N256: case HB_N512: case HB_COLS512: case HB_ROWS512: case HB_N128_B: return 32;
+        case HB_N1024: case HB_N256_B: case HB_N512_B: return 16;
         case HB_N2048: case HB_N1024_B: return 8;
-        case HB_N4096_B: return 4;
+        case HB_N4096_B: case HB_N2048_B: return 4;
         case HB_N16384: return 1;
         default: return 2;       // HB_N4096, HB_N8192
     }
@@ -377,7 +379,9 @@ int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s) {
     return FFT_OK;
 }
 
-fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, const int* choice) {
+// alt: per log2 N (0 .. kMaxSingleLog), 1 to take kAltCfg instead of
+// kSmallCfg (NULL: every class its default).
+fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, const int* alt) {
     if (!n || count < 1) {
         set_error(FFT_EINVAL, "need at least one transform");
         return nullptr;
@@ -407,10 +411,9 @@ fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, co
         nmax = std::max(nmax, v);
     }
     for (int m = 1; m <= kMaxSingleLog; ++m) b->cfg_choice[m] = kSmallCfg[m];
-    if (choice) {
-        if (choice[0] == HB_N1024 || choice[0] == HB_N1024_B) b->cfg_choice[10] = choice[0];
-        if (choice[1] == HB_N4096 || choice[1] == HB_N4096_B) b->cfg_choice[12] = choice[1];
-    }
+    if (alt)
+        for (int m = 1; m <= kMaxSingleLog; ++m)
+            if (alt[m] == 1 && kAltCfg[m] >= 0) b->cfg_choice[m] = kAltCfg[m];
     hipError_t e = hipGetDevice(&b->device);
     if (e != hipSuccess) {
         hip_error(e, "hipGetDevice");
@@ -434,9 +437,18 @@ fft_batch* fft_batch_create(const int64_t* n, int64_t count, fft_dtype dtype, ff
 
 fft_batch* fft_batch_create_tuned(const int64_t* n, int64_t count, fft_dtype dtype,
                                   fft_table_kind kind, int choice_1024, int choice_4096) {
-    const int c[2] = {choice_1024 == 1 ? HB_N1024_B : HB_N1024,
-                      choice_4096 == 1 ? HB_N4096_B : HB_N4096};
-    return batch_create(n, count, (int)dtype, (int)kind, c);
+    int alt[kMaxSingleLog + 1] = {};
+    alt[10] = choice_1024 == 1;
+    alt[12] = choice_4096 == 1;
+    return batch_create(n, count, (int)dtype, (int)kind, alt);
+}
+
+fft_batch* fft_batch_create_classes(const int64_t* n, int64_t count, fft_dtype dtype,
+                                    fft_table_kind kind, const int32_t* alt) {
+    int a[kMaxSingleLog + 1] = {};
+    if (alt)
+        for (int m = 1; m <= kMaxSingleLog; ++m) a[m] = alt[m] == 1;
+    return batch_create(n, count, (int)dtype, (int)kind, a);
 }
 
 int fft_batch_execute(fft_batch* b, const void* in, void* out, void* stream) {

@@ -23,6 +23,7 @@ enum HostBatchCfg {
     HB_N2048, HB_N4096, HB_N8192,
     HB_N1024_B, HB_N4096_B,
     HB_ROWS128, HB_COLS256, HB_ROWS256, HB_COLS512, HB_ROWS512, HB_N16384,
+    HB_N128_B, HB_N256_B, HB_N512_B, HB_N2048_B,
     HB_COUNT
 };
 
@@ -42,6 +43,10 @@ constexpr int kListThreads = 1024;
 inline int lists_for(int dtype) { return dtype == 0 ? kNumLists : 0; }
 inline int max_whole_log(int dtype) { return dtype == 0 ? kListLog[0] : kMaxSingleLog; }
 extern const int kSmallCfg[kMaxSingleLog + 1];   // their configuration per log2 N (1..14)
+// The alternative configuration per log2 N that the batch tuner weighs
+// against kSmallCfg (another radix split, units per workgroup and elements per
+// lane), -1 where there is none.
+extern const int kAltCfg[kMaxSingleLog + 1];
 int cfg_upw(int cfg);                  // units per workgroup of a configuration
 
 // Work list for transforms of sizes n[t] at element offsets off[t] (batch.cpp):

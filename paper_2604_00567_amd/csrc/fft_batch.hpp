@@ -125,7 +125,9 @@ constexpr int batch_lds_elems() {
         2 * PassPlan<13, 5, 4, 4>::region(), 8 * PassPlan<10, 4, 3, 3>::region(),
         4 * PassPlan<12, 5, 4, 3>::region(), 64 * PassPlan<7, 4, 3, 0>::region(),
         64 * PassPlan<8, 5, 3, 0>::region(), 32 * PassPlan<9, 5, 4, 0>::region(),
-        1 * PassPlan<14, 5, 5, 4>::region()};
+        1 * PassPlan<14, 5, 5, 4>::region(), 32 * PassPlan<7, 3, 2, 2>::region(),
+        16 * PassPlan<8, 3, 3, 2>::region(), 16 * PassPlan<9, 4, 3, 2>::region(),
+        4 * PassPlan<11, 4, 4, 3>::region()};
     for (int s : sizes) m = s > m ? s : m;
     return m;
 }
@@ -156,6 +158,10 @@ __device__ __forceinline__ void batch_dispatch(int cfg, E* lds,
         case HB_COLS512: batch_unit<E, 9, 5, 32, MODE_COLS, 5, 4, 0>(lds, lt, in, ws, g); break;
         case HB_ROWS512: batch_unit<E, 9, 5, 32, MODE_ROWS, 5, 4, 0>(lds, lt, ws, out, g); break;
         case HB_N16384: batch_unit<E, 14, 5, 1, MODE_SMALL, 5, 5, 4>(lds, lt, in, out, g); break;
+        case HB_N128_B: batch_unit<E, 7, 3, 32, MODE_SMALL, 3, 2, 2>(lds, lt, in, out, g); break;
+        case HB_N256_B: batch_unit<E, 8, 3, 16, MODE_SMALL, 3, 3, 2>(lds, lt, in, out, g); break;
+        case HB_N512_B: batch_unit<E, 9, 4, 16, MODE_SMALL, 4, 3, 2>(lds, lt, in, out, g); break;
+        case HB_N2048_B: batch_unit<E, 11, 4, 4, MODE_SMALL, 4, 4, 3>(lds, lt, in, out, g); break;
         default: break;
     }
 }

@@ -347,8 +347,11 @@ __device__ __forceinline__ void store_elem(E v, S* p) {
     else *p = s;
 }
 
-// Whole-transform blocks (a workgroup's units contiguous in memory) move
-// through a buffer resource over the block: each access is the lane's 32-bit
+// Whole-transform blocks (a workgroup's units contiguous in memory) of units
+// larger than 4 KiB move through a buffer resource over the block (smaller
+// units address every element with the global instructions' immediate
+// offset, and their one-transform-per-lane patterns measured several times
+// slower through buffer instructions): each access is the lane's 32-bit
 // byte offset plus a compile-time offset held in a scalar register, so no
 // per-access 64-bit address arithmetic runs on the vector ALU (which the
 // largest transforms, at 6 FMAs per byte, cannot spare), and accesses past
@@ -784,7 +787,7 @@ __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
     const int tid = gp.tid();
     const int ul0 = unit_fast ? (tid % UPW) : (tid / G) * UPL;
     const int g = unit_fast ? (tid / UPW) : (tid % G);
-    if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc) {
+    if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc && NU * sizeof(SI) > 4096) {
         const rsrc_t rs = block_rsrc(in + gp.block_first(LOG_NU), gp.block_units(UPW) << LOG_NU);
 #pragma unroll
         for (int k = 0; k < UPL; ++k) {
@@ -1160,7 +1163,7 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
             __syncthreads();
             stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
                                                gp.block_units(UPW) << LOG_NU);
-        } else if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc) {
+        } else if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc && NU * sizeof(SO) > 4096) {
             const rsrc_t rs = block_rsrc(out + gp.block_first(LOG_NU), gp.block_units(UPW) << LOG_NU);
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {

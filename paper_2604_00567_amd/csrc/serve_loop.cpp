@@ -5,8 +5,8 @@
 //                  into a free slot while they fit the HBM budget and the
 //                  slot's capacities, and each slot runs one step per
 //                  precision (the serving-slot batch kernels, or, for a step of
-//                  at most direct_max whole-size requests, one cached-plan
-//                  launch per request); steps on different slots overlap.
+//                  at most direct_max requests, one cached-plan launch per
+//                  request); steps on different slots overlap.
 //   per request    one cached-plan launch per request, round-robin over K
 //                  streams, admitted in arrival order under the same budget.
 //
@@ -159,11 +159,14 @@ struct EventPool {
 // Admission of one step (continuous loop): requests from `head` on, in arrival
 // order, while each fits the budget (request bytes, plus workspace for split
 // transforms, on top of what is in flight) and the step's capacities.
+// At most `limit` requests (and max_step_requests).
 int64_t serve_admit(const Trace& tr, const int64_t* order, int64_t avail, int64_t head, size_t inflight,
-                    const fft_serve_config& c, std::vector<int64_t>& take, size_t* inflight_out) {
+                    const fft_serve_config& c, std::vector<int64_t>& take, size_t* inflight_out,
+                    int64_t limit) {
     StepLoad ld;
     take.clear();
-    while (head < avail && (int64_t)take.size() < c.max_step_requests) {
+    limit = std::min<int64_t>(limit, c.max_step_requests);
+    while (head < avail && (int64_t)take.size() < limit) {
         const int64_t r = order[head];
         const int64_t n = tr.n[r], b = tr.b[r];
         const int dt = tr.dtype[r], d = dt_index(dt);
@@ -265,7 +268,7 @@ int fft_serve_admit(const int64_t* n, const int64_t* batch, const int32_t* dtype
     std::vector<int64_t> order(count), take;
     for (int64_t i = 0; i < count; ++i) order[i] = i;
     Trace tr{nullptr, n, batch, dtype, count};
-    serve_admit(tr, order.data(), count, head, inflight_bytes, *cfg, take, inflight_out);
+    serve_admit(tr, order.data(), count, head, inflight_bytes, *cfg, take, inflight_out, cfg->max_step_requests);
     std::copy(take.begin(), take.end(), taken);
     *ntaken = (int64_t)take.size();
     return FFT_OK;
@@ -320,12 +323,22 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                 if (s.done) (void)hipEventDestroy(s.done);
                 if (s.st) (void)hipStreamDestroy(s.st);
             }
+            for (void* w : plans.ws) (void)hipFree(w);
+            plans.ws.clear();
         };
         for (auto& s : slots) {
             if ((e = hipStreamCreate(&s.st)) != hipSuccess || (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
                 cleanup();
                 return hip_error(e, "slot stream/event");
             }
+            // workspace of the slot's direct two-pass launches (its steps are
+            // ordered on its stream)
+            void* w = nullptr;
+            if ((e = hipMalloc(&w, kMaxWorkspaceBytes)) != hipSuccess) {
+                cleanup();
+                return set_error(e == hipErrorOutOfMemory ? FFT_ENOMEM : FFT_EHIP, "workspace allocation failed");
+            }
+            plans.ws.push_back(w);
             for (int d = 0; d < 2; ++d) {
                 const int dt = d == 0 ? DT_F16 : DT_F32;
                 if ((e = hipMalloc(&s.arena[d], c.slot_bytes)) != hipSuccess) {
@@ -372,17 +385,23 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                 progressed = true;
             }
             if (rc != FFT_OK) break;
-            for (auto& s : slots) {
+            // waiting requests are spread over the free slots (a step takes its
+            // share, rounded up), so that at low load requests run on separate
+            // streams instead of one after another in one step
+            int free_slots = 0;
+            for (auto& x : slots) free_slots += x.busy ? 0 : 1;
+            for (size_t si = 0; si < slots.size(); ++si) {
+                Slot& s = slots[si];
                 if (s.busy || head >= nxt) continue;
                 size_t infl2 = inflight;
-                head = serve_admit(tr, order.data(), nxt, head, inflight, c, take, &infl2);
+                const int64_t share = (nxt - head + free_slots - 1) / std::max(free_slots, 1);
+                --free_slots;
+                head = serve_admit(tr, order.data(), nxt, head, inflight, c, take, &infl2, share);
                 if (take.empty()) continue;
                 inflight = infl2;
                 // placement per precision, in admission order
                 int64_t used[2] = {0, 0};
-                bool any_split = false;
-                for (int64_t r : take) any_split |= is_split(n[r], dtype[r]);
-                const bool direct = (int64_t)take.size() <= c.direct_max && !any_split;
+                const bool direct = (int64_t)take.size() <= c.direct_max;
                 for (int d = 0; d < 2 && rc == FFT_OK; ++d) {
                     const int dt = d == 0 ? DT_F16 : DT_F32;
                     tn.clear();
@@ -406,7 +425,8 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                     }
                     if (direct) {
                         for (size_t i = 0; i < tn.size() && rc == FFT_OK; ++i) {
-                            fft_plan* p = plans.get(tn[i], tb[i], dt, 0);
+                            // split sizes: a plan per slot, on the slot's workspace
+                            fft_plan* p = plans.get(tn[i], tb[i], dt, is_split(tn[i], dt) ? (int)si : 0);
                             if (!p) {
                                 rc = FFT_ENOMEM;
                                 break;

@@ -240,27 +240,27 @@ int fft_tuned_choice(int64_t n, fft_dtype dtype, int* variant_a, int* variant_b,
 }  // extern "C"
 
 namespace dsfft {
-fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, const int* choice);
+fft_batch* batch_create(const int64_t* n, int64_t count, int dtype, int kind, const int* alt);
 int batch_execute(fft_batch* b, const void* in, void* out, hipStream_t s);
 }  // namespace dsfft
 
 extern "C" {
 
-// Per size class of the uneven-batch kernel that has alternatives (2^10 and
-// 2^12): times a batch of that class alone with each configuration (HIP
-// events, `reps` graph replays), requires bit-identical outputs, and returns
-// the faster choice (0 or 1) for fft_batch_create_tuned.
-int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1024,
-                   int* choice_4096) {
-    if (reps < 1 || !choice_1024 || !choice_4096) return set_error(FFT_EINVAL, "bad tuning request");
-    int* out[2] = {choice_1024, choice_4096};
-    const int64_t sizes[2] = {1024, 4096};
-    for (int cls = 0; cls < 2; ++cls) {
-        const int64_t n = sizes[cls], count = (int64_t(1) << 24) / n;   // 2^24 elements
+// Per size class of the uneven-batch kernel with an alternative configuration
+// (kAltCfg): times a batch of that class alone (2^24 elements) with each
+// configuration (HIP events, `reps` graph replays), requires the outputs to be
+// bit-identical, and sets alt_out[m] to 1 where the alternative is faster.
+int fft_batch_tune_classes(fft_dtype dtype, fft_table_kind kind, int reps, int32_t* alt_out) {
+    if (reps < 1 || !alt_out) return set_error(FFT_EINVAL, "bad tuning request");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32) return set_error(FFT_EINVAL, "dtype must be FFT_F16 or FFT_F32");
+    for (int m = 0; m <= kMaxSingleLog; ++m) alt_out[m] = 0;
+    for (int m = 1; m <= kMaxSingleLog; ++m) {
+        if (kAltCfg[m] < 0) continue;
+        const int64_t n = int64_t(1) << m, count = (int64_t(1) << 24) / n;   // 2^24 elements
         std::vector<int64_t> ns((size_t)count, n);
         const size_t bytes = (size_t)n * count * elem_bytes((int)dtype);
         std::vector<uint8_t> host(bytes), ref(bytes), got(bytes);
-        fill_synthetic(host, (int)dtype, 977 + cls);
+        fill_synthetic(host, (int)dtype, 977 + m);
         void *din = nullptr, *dout = nullptr;
         hipStream_t st = nullptr;
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -277,11 +277,10 @@ int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1
             return hip_error(e, "batch tuning setup");
         }
         float best = 1e30f;
-        *out[cls] = 0;
         for (int alt = 0; alt < 2; ++alt) {
-            const int c[2] = {cls == 0 ? (alt ? HB_N1024_B : HB_N1024) : HB_N1024,
-                              cls == 1 ? (alt ? HB_N4096_B : HB_N4096) : HB_N4096};
-            fft_batch* b = batch_create(ns.data(), count, (int)dtype, (int)kind, c);
+            int a[kMaxSingleLog + 1] = {};
+            a[m] = alt;
+            fft_batch* b = batch_create(ns.data(), count, (int)dtype, (int)kind, a);
             if (!b) continue;
             bool ok = batch_execute(b, din, dout, st) == FFT_OK && hipStreamSynchronize(st) == hipSuccess;
             ok = ok && hipMemcpy(alt == 0 ? ref.data() : got.data(), dout, bytes, hipMemcpyDeviceToHost) == hipSuccess;
@@ -296,7 +295,7 @@ int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1
             fft_batch_destroy(b);
             if (ok && ms < best) {
                 best = ms;
-                *out[cls] = alt;
+                alt_out[m] = alt;
             }
         }
         (void)hipFree(din);
@@ -305,6 +304,18 @@ int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
+    return FFT_OK;
+}
+
+// The 2^10 and 2^12 classes' choices of fft_batch_tune_classes.
+int fft_batch_tune(fft_dtype dtype, fft_table_kind kind, int reps, int* choice_1024,
+                   int* choice_4096) {
+    if (!choice_1024 || !choice_4096) return set_error(FFT_EINVAL, "bad tuning request");
+    int32_t alt[kMaxSingleLog + 1];
+    const int rc = fft_batch_tune_classes(dtype, kind, reps, alt);
+    if (rc != FFT_OK) return rc;
+    *choice_1024 = alt[10];
+    *choice_4096 = alt[12];
     return FFT_OK;
 }
 

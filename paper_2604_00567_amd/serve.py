@@ -5,8 +5,8 @@ Requests (N = 2^k up to 2^18 points, a batch of such transforms, binary16 or
 binary32) arrive over time.  The continuous loop admits them in arrival order
 whenever one of K slots is free and they fit the HBM budget, generates their
 data on the device, and launches one step per precision on the slot's stream
-(the serving-slot batch kernels, or for a step of one or two whole-size
-requests one cached-plan launch each); K slots run on K streams, so a step
+(the serving-slot batch kernels, or for a step of one or two requests one
+cached-plan launch each); K slots run on K streams, so a step
 admitted while earlier steps are still on the GPU overlaps with them.
 ``run_per_request`` replays the same trace with one cached-plan launch per
 request, the form the continuous loop is compared with.  Latency of a request
@@ -103,8 +103,8 @@ class Server:
     """K-slot continuous-batching server (``fft_serve_run``, continuous mode).
     ``budget_bytes`` caps the request data (plus large-transform workspace)
     admitted but not yet completed.  A step of at most ``direct_max``
-    requests that all run whole launches each through a cached plan; larger
-    steps run the slot's batch kernels.  Both forms compute every transform
+    requests launches each through a cached plan (two-pass plans on a
+    workspace of the slot); larger steps run the slot's batch kernels.  Both forms compute every transform
     with the same butterflies and table, bit for bit."""
 
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, slot_bytes: int = 1 << 30,

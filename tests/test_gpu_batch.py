@@ -115,6 +115,20 @@ def test_tuned_alternatives_bit_identical(choice):
     check_all(sizes, x, y, "f16")
 
 
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_class_alternatives_bit_identical(dtype):
+    # every class with an alternative configuration (2^7 .. 2^12) takes it,
+    # ragged against each configuration's units per workgroup; the oracle decides
+    alt = [0] * 15
+    for m in range(7, 13):
+        alt[m] = 1
+    sizes = np.array([128] * 35 + [256] * 19 + [512] * 21 + [1024] * 9 + [2048] * 7 + [4096] * 5 + [64] * 3,
+                     dtype=np.int64)
+    x = inputs.packed_uniform(sizes, 62, dtype)
+    (y,), _ = run_batch(sizes, x, dtype, choice=alt)
+    check_all(sizes, x, y, dtype)
+
+
 def test_batch_argument_errors():
     for bad in ([3], [1 << 19], [0], []):
         with pytest.raises(binding.FFTError):

@@ -52,3 +52,9 @@ def test_small_batch_takes_one_transform_per_workgroup(dtype):
 def test_batch_tune_returns_choices():
     a, b = binding.fft_batch_tune("f16", "dual_select", reps=3)
     assert a in (0, 1) and b in (0, 1)
+
+
+def test_batch_tune_classes_returns_choices():
+    alt = binding.fft_batch_tune_classes("f16", "dual_select", reps=2)
+    assert len(alt) == 15 and set(alt) <= {0, 1}
+    assert all(alt[m] == 0 for m in list(range(0, 7)) + [13, 14])   # classes without an alternative

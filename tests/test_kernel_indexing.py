@@ -436,7 +436,7 @@ def load_batch_configs():
 
 def test_batch_configs_parsed():
     cfgs = load_batch_configs()
-    assert len(cfgs) == 21
+    assert len(cfgs) == 25
     for name, c in cfgs.items():
         assert c[3] << (c[1] - c[2]) == 512, name       # every configuration uses 512 threads
         assert sum(c[4:7]) == c[1], name
