@@ -52,7 +52,7 @@ class ServeConfig(ctypes.Structure):
                 ("direct_max", ctypes.c_int), ("max_step_requests", ctypes.c_int),
                 ("max_large", ctypes.c_int), ("max_transforms", ctypes.c_int64),
                 ("max_items", ctypes.c_int64), ("budget_bytes", ctypes.c_size_t),
-                ("slot_bytes", ctypes.c_size_t), ("seed", ctypes.c_uint64)]
+                ("slot_bytes", ctypes.c_size_t), ("seed", ctypes.c_uint64), ("split_direct", ctypes.c_int)]
 
 
 class ServeStats(ctypes.Structure):

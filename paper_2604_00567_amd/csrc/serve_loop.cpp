@@ -205,8 +205,27 @@ struct Slot {
     void* arena[2] = {nullptr, nullptr};
     fft_serve_slot* native[2] = {nullptr, nullptr};
     hipEvent_t done = nullptr;
-    bool busy = false;
-    std::vector<int64_t> rids;
+    hipEvent_t early = nullptr;      // the step's whole-size requests (split_direct)
+    bool busy = false, early_busy = false;
+    std::vector<int64_t> rids, early_rids;
+};
+
+// One precision's requests of a step, in admission order, with their element
+// offsets in the slot's arena.
+struct Group {
+    std::vector<int64_t> rid, n, b, off;
+    void clear() {
+        rid.clear();
+        n.clear();
+        b.clear();
+        off.clear();
+    }
+    void add(int64_t r, int64_t nn, int64_t bb, int64_t o) {
+        rid.push_back(r);
+        n.push_back(nn);
+        b.push_back(bb);
+        off.push_back(o);
+    }
 };
 
 struct Inflight {
@@ -321,13 +340,15 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                     if (s.arena[d]) (void)hipFree(s.arena[d]);
                 }
                 if (s.done) (void)hipEventDestroy(s.done);
+                if (s.early) (void)hipEventDestroy(s.early);
                 if (s.st) (void)hipStreamDestroy(s.st);
             }
             for (void* w : plans.ws) (void)hipFree(w);
             plans.ws.clear();
         };
         for (auto& s : slots) {
-            if ((e = hipStreamCreate(&s.st)) != hipSuccess || (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
+            if ((e = hipStreamCreate(&s.st)) != hipSuccess || (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&s.early, hipEventDisableTiming)) != hipSuccess) {
                 cleanup();
                 return hip_error(e, "slot stream/event");
             }
@@ -359,29 +380,45 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
         }
         int64_t nxt = 0, head = 0, completed = 0;
         size_t inflight = 0;
-        std::vector<int64_t> take, tn, tb, to;
+        std::vector<int64_t> take;
+        Group whole[2], split[2];
         double sum_req = 0;
         const Clock::time_point t0 = Clock::now();
+        auto retire = [&](std::vector<int64_t>& rids) {
+            const double td = seconds_since(t0);
+            for (int64_t r : rids) {
+                done_t[r] = td;
+                inflight -= 2 * (size_t)n[r] * batch[r] * ebytes(dtype[r]);
+            }
+            completed += (int64_t)rids.size();
+            rids.clear();
+        };
         while (completed < count && rc == FFT_OK) {
             const double now = seconds_since(t0);
             while (nxt < count && t[nxt] <= now) ++nxt;
             bool progressed = false;
             for (auto& s : slots) {
                 if (!s.busy) continue;
+                if (s.early_busy) {
+                    e = hipEventQuery(s.early);
+                    if (e == hipSuccess) {
+                        retire(s.early_rids);
+                        s.early_busy = false;
+                        progressed = true;
+                    } else if (e != hipErrorNotReady) {
+                        rc = hip_error(e, "hipEventQuery");
+                        break;
+                    }
+                }
                 e = hipEventQuery(s.done);
                 if (e == hipErrorNotReady) continue;
                 if (e != hipSuccess) {
                     rc = hip_error(e, "hipEventQuery");
                     break;
                 }
-                const double td = seconds_since(t0);
-                for (int64_t r : s.rids) {
-                    done_t[r] = td;
-                    inflight -= 2 * (size_t)n[r] * batch[r] * ebytes(dtype[r]);
-                }
-                completed += (int64_t)s.rids.size();
-                s.busy = false;
-                s.rids.clear();
+                if (s.early_busy) retire(s.early_rids);
+                retire(s.rids);
+                s.busy = s.early_busy = false;
                 progressed = true;
             }
             if (rc != FFT_OK) break;
@@ -399,66 +436,83 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                 head = serve_admit(tr, order.data(), nxt, head, inflight, c, take, &infl2, share);
                 if (take.empty()) continue;
                 inflight = infl2;
-                // placement per precision, in admission order
-                int64_t used[2] = {0, 0};
+                // placement per precision in admission order; split transforms
+                // form their own group when they run through their plans
                 const bool direct = (int64_t)take.size() <= c.direct_max;
+                int64_t used[2] = {0, 0};
+                uint64_t gen_first[2] = {0, 0};
+                for (int d = 0; d < 2; ++d) {
+                    whole[d].clear();
+                    split[d].clear();
+                }
+                for (int64_t r : take) {
+                    const int d = dt_index(dtype[r]);
+                    if (used[d] == 0) gen_first[d] = first[r];
+                    Group& g = c.split_direct && is_split(n[r], dtype[r]) ? split[d] : whole[d];
+                    g.add(r, n[r], batch[r], used[d]);
+                    used[d] += n[r] * batch[r];
+                }
+                // the step's requests of one precision are consecutive in that
+                // precision's arrival order: one generator launch covers them
                 for (int d = 0; d < 2 && rc == FFT_OK; ++d) {
-                    const int dt = d == 0 ? DT_F16 : DT_F32;
-                    tn.clear();
-                    tb.clear();
-                    to.clear();
-                    uint64_t gen_first = 0;
-                    for (int64_t r : take) {
-                        if (dtype[r] != dt) continue;
-                        if (tn.empty()) gen_first = first[r];
-                        tn.push_back(n[r]);
-                        tb.push_back(batch[r]);
-                        to.push_back(used[d]);
-                        used[d] += n[r] * batch[r];
-                    }
-                    if (tn.empty()) continue;
-                    // the step's requests of one precision are consecutive in that
-                    // precision's arrival order: one generator launch covers them
-                    if ((e = fill_normal(dt, s.arena[d], used[d], gen_first, c.seed, s.st)) != hipSuccess) {
+                    if (used[d] && (e = fill_normal(d == 0 ? DT_F16 : DT_F32, s.arena[d], used[d], gen_first[d], c.seed,
+                                                    s.st)) != hipSuccess)
                         rc = hip_error(e, "launch(fill)");
-                        break;
-                    }
-                    if (direct) {
-                        for (size_t i = 0; i < tn.size() && rc == FFT_OK; ++i) {
-                            // split sizes: a plan per slot, on the slot's workspace
-                            fft_plan* p = plans.get(tn[i], tb[i], dt, is_split(tn[i], dt) ? (int)si : 0);
-                            if (!p) {
-                                rc = FFT_ENOMEM;
-                                break;
+                }
+                // one group's transforms: cached plans (split sizes: a plan per
+                // slot, on the slot's workspace) or the slot's kernels; then the
+                // optional output copies
+                auto run_group = [&](Group* gs, bool plans_only) {
+                    for (int d = 0; d < 2 && rc == FFT_OK; ++d) {
+                        const Group& g = gs[d];
+                        if (g.rid.empty()) continue;
+                        const int dt = d == 0 ? DT_F16 : DT_F32;
+                        if (plans_only) {
+                            for (size_t i = 0; i < g.rid.size() && rc == FFT_OK; ++i) {
+                                fft_plan* p = plans.get(g.n[i], g.b[i], dt, is_split(g.n[i], dt) ? (int)si : 0);
+                                if (!p) {
+                                    rc = FFT_ENOMEM;
+                                    break;
+                                }
+                                char* ptr = (char*)s.arena[d] + (size_t)g.off[i] * ebytes(dt);
+                                rc = plan_execute(p, ptr, ptr, s.st);
                             }
-                            char* ptr = (char*)s.arena[d] + (size_t)to[i] * ebytes(dt);
-                            rc = plan_execute(p, ptr, ptr, s.st);
+                        } else {
+                            rc = fft_serve_slot_launch(s.native[d], g.n.data(), g.b.data(), g.off.data(),
+                                                       (int64_t)g.rid.size(), s.arena[d], s.st);
                         }
-                    } else {
-                        rc = fft_serve_slot_launch(s.native[d], tn.data(), tb.data(), to.data(), (int64_t)tn.size(),
-                                                   s.arena[d], s.st);
-                    }
-                    if (rc == FFT_OK && out_dev && out_off) {
-                        size_t k = 0;
-                        for (int64_t r : take) {
-                            if (dtype[r] != dt) continue;
+                        if (rc != FFT_OK || !out_dev || !out_off) continue;
+                        for (size_t i = 0; i < g.rid.size(); ++i) {
+                            const int64_t r = g.rid[i];
                             const size_t len = (size_t)n[r] * batch[r] * ebytes(dt);
-                            if ((e = hipMemcpyAsync((char*)out_dev + out_off[r], (char*)s.arena[d] + (size_t)to[k] * ebytes(dt),
+                            if ((e = hipMemcpyAsync((char*)out_dev + out_off[r], (char*)s.arena[d] + (size_t)g.off[i] * ebytes(dt),
                                                     len, hipMemcpyDeviceToDevice, s.st)) != hipSuccess) {
                                 rc = hip_error(e, "hipMemcpyAsync(output)");
                                 break;
                             }
-                            ++k;
                         }
                     }
+                };
+                run_group(whole, direct);
+                s.rids.clear();
+                s.early_rids.clear();
+                const bool two = (!whole[0].rid.empty() || !whole[1].rid.empty()) &&
+                                 (!split[0].rid.empty() || !split[1].rid.empty());
+                for (int d = 0; d < 2; ++d) {
+                    std::vector<int64_t>& dst = two ? s.early_rids : s.rids;
+                    dst.insert(dst.end(), whole[d].rid.begin(), whole[d].rid.end());
+                    s.rids.insert(s.rids.end(), split[d].rid.begin(), split[d].rid.end());
                 }
+                if (rc == FFT_OK && two && (e = hipEventRecord(s.early, s.st)) != hipSuccess)
+                    rc = hip_error(e, "hipEventRecord");
+                if (rc == FFT_OK) run_group(split, true);
                 if (rc != FFT_OK) break;
                 if ((e = hipEventRecord(s.done, s.st)) != hipSuccess) {
                     rc = hip_error(e, "hipEventRecord");
                     break;
                 }
                 s.busy = true;
-                s.rids = take;
+                s.early_busy = two;
                 st.steps += 1;
                 st.direct_steps += direct ? 1 : 0;
                 sum_req += (double)take.size();

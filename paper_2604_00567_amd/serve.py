@@ -6,7 +6,8 @@ binary32) arrive over time.  The continuous loop admits them in arrival order
 whenever one of K slots is free and they fit the HBM budget, generates their
 data on the device, and launches one step per precision on the slot's stream
 (the serving-slot batch kernels, or for a step of one or two requests one
-cached-plan launch each); K slots run on K streams, so a step
+cached-plan launch each; split-size transforms through their cached two-pass
+plans); K slots run on K streams, so a step
 admitted while earlier steps are still on the GPU overlaps with them.
 ``run_per_request`` replays the same trace with one cached-plan launch per
 request, the form the continuous loop is compared with.  Latency of a request
@@ -104,15 +105,19 @@ class Server:
     ``budget_bytes`` caps the request data (plus large-transform workspace)
     admitted but not yet completed.  A step of at most ``direct_max``
     requests launches each through a cached plan (two-pass plans on a
-    workspace of the slot); larger steps run the slot's batch kernels.  Both forms compute every transform
-    with the same butterflies and table, bit for bit."""
+    workspace of the slot); larger steps run the slot's batch kernels.  With
+    ``split_direct`` the split-size transforms (column/row schedule) of every
+    step take their cached two-pass plans after the step's other requests,
+    which complete on an event of their own.  All forms compute every
+    transform with the same butterflies and table, bit for bit."""
 
     def __init__(self, slots: int = 4, budget_bytes: int = 64 << 30, slot_bytes: int = 1 << 30,
                  kind: str = "dual_select", max_transforms: int = 1 << 15,
                  max_large: int = 1 << 12, max_items: int = 1 << 18, seed: int = 0,
-                 keep_io: bool = False, direct_max: int = 2):
+                 keep_io: bool = False, direct_max: int = 2, split_direct: bool = True):
         self.slots, self.budget, self.slot_bytes = int(slots), int(budget_bytes), int(slot_bytes)
         self.kind, self.seed, self.keep_io, self.direct_max = kind, int(seed), keep_io, int(direct_max)
+        self.split_direct = bool(split_direct)
         self.max_transforms, self.max_large, self.max_items = int(max_transforms), int(max_large), int(max_items)
         self.inputs, self.outputs = {}, {}
 
@@ -121,7 +126,7 @@ class Server:
             mode=binding.FFT_SERVE_CONTINUOUS, slots=self.slots, kind=binding.KINDS[self.kind],
             direct_max=self.direct_max, max_step_requests=int(max_step_requests), max_large=self.max_large,
             max_transforms=self.max_transforms, max_items=self.max_items, budget_bytes=self.budget,
-            slot_bytes=self.slot_bytes, seed=self.seed)
+            slot_bytes=self.slot_bytes, seed=self.seed, split_direct=int(self.split_direct))
 
     def run(self, trace: dict, max_step_requests: int = 256) -> dict:
         cfg = self.config(max_step_requests)
@@ -134,7 +139,8 @@ class Server:
         return _summary(trace, done, st, {
             "steps": int(st.steps), "mean_requests_per_step": float(st.mean_requests_per_step),
             "budget_bytes": self.budget, "max_concurrent_steps": int(st.max_concurrent),
-            "slots": self.slots, "direct_steps": int(st.direct_steps), "direct_max": self.direct_max})
+            "slots": self.slots, "direct_steps": int(st.direct_steps), "direct_max": self.direct_max,
+            "split_direct": self.split_direct})
 
     def close(self):
         """Nothing to release: each run allocates and frees its own slots.  The

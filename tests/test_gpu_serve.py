@@ -152,10 +152,11 @@ def test_large_requests_alone_equal_results_in_mix():
     the column/row split of binary16 2^17-2^18 and binary32 2^15-2^18 runs in
     the slots' batch kernels beside whole transforms; every split-size request
     and a sample of the others equal a regular plan on the same input, and a
-    few equal the oracle's emulation."""
+    few equal the oracle's emulation.  Running the split transforms through
+    their two-pass plans instead gives every request the same output."""
     import torch
     tr = small_trace(160, 31, rate=400000.0, log_hi=18, batch_hi=64)
-    srv = Server(slots=3, slot_bytes=512 << 20, keep_io=True, seed=9)
+    srv = Server(slots=3, slot_bytes=512 << 20, keep_io=True, seed=9, split_direct=False)
     try:
         stats = srv.run(tr, max_step_requests=32)
         torch.cuda.synchronize()
@@ -163,6 +164,15 @@ def test_large_requests_alone_equal_results_in_mix():
         srv.close()
     assert stats["requests"] == tr["t"].size
     assert stats["mean_requests_per_step"] > 1.0
+    # split transforms through their two-pass plans, the rest of each step
+    # completing on its own event: the same outputs bit for bit
+    srv2 = Server(slots=3, slot_bytes=512 << 20, keep_io=True, seed=9, split_direct=True)
+    stats2 = srv2.run(tr, max_step_requests=32)
+    torch.cuda.synchronize()
+    assert stats2["requests"] == tr["t"].size and stats2["mean_requests_per_step"] > 1.0
+    for rid in range(tr["t"].size):
+        assert mismatches(srv2.outputs[rid].cpu().numpy(), srv.outputs[rid].cpu().numpy()) == 0, rid
+    del srv2
     n_all, b_all, d_all = tr["n"], tr["batch"], tr["dtype"]
     split_ids = [r for r in range(tr["t"].size)
                  if n_all[r] > (1 << (16 if d_all[r] == "f16" else 14))]
