@@ -571,9 +571,9 @@ def main():
         result["single_fp32"] = bench_single_fp32(torch, binding, inputs)
         torch.cuda.empty_cache()
         if args.serve_seconds > 0:
-            log(f"serving, {args.serve_seconds:g} s of trace at 20k req/s, 2 s at 80k req/s")
+            log(f"serving, {args.serve_seconds:g} s of trace at 20k req/s, 4 s at 80k req/s")
             result["serving"] = bench_serving(torch, args.serve_seconds)
-            result["serving_high_load"] = bench_serving(torch, 2.0, seed=10, rate=80000.0)
+            result["serving_high_load"] = bench_serving(torch, 4.0, seed=10, rate=80000.0)
     bufs.clear()
     if not args.no_cpu:
         log("cpu baseline (oracle FP64 FFT)")
