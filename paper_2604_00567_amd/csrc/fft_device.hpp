@@ -479,6 +479,7 @@ enum { MODE_SMALL = 0, MODE_COLS = 1, MODE_ROWS = 2 };
 
 template <int LOG_NU, int LR0, int LR1, int LR2, int LANE = 0>
 struct PassPlan {
+    static constexpr int log_nu = LOG_NU;
     static constexpr int NP = LR1 == 0 ? 1 : (LR2 == 0 ? 2 : 3);
     static constexpr int lr(int p) { return p == 0 ? LR0 : (p == 1 ? LR1 : LR2); }
     // log2 of the span before pass p
@@ -513,13 +514,19 @@ struct PassPlan {
 // Exchanges in two rounds: a whole-transform unit (one per workgroup) whose
 // exchange would not fit in LDS writes and reads half of the exchange's rows
 // per round (binary16 2^16 points: 256 KiB of data, 128-135 KiB per round).
-// Each pass after an exchange must hold at least two groups per lane (the
-// rounds split a lane's groups in halves).
+// A binary16 2^15-point unit held as 64 elements on each of 512 lanes also
+// exchanges in two rounds although one would fit: 70 KiB of LDS instead of
+// 135, so two such workgroups share a CU.  Each pass after an exchange must
+// hold at least two groups per lane (the rounds split a lane's groups in
+// halves).
 constexpr size_t kLdsBytes = 160 * 1024;
 template <class E, int LOG_E, int MODE, int UPW, class PP>
 constexpr int exchange_rounds() {
-    if (!(MODE == MODE_SMALL && UPW == 1 && PP::NP > 1 && (size_t)PP::region() * sizeof(E) > kLdsBytes))
+    if (!(MODE == MODE_SMALL && UPW == 1 && PP::NP > 1))
         return 1;
+    const bool over = (size_t)PP::region() * sizeof(E) > kLdsBytes;
+    const bool shared = sizeof(E) == 4 && LOG_E == 6 && PP::log_nu == 15;
+    if (!over && !shared) return 1;
     for (int p = 1; p < PP::NP; ++p)
         if (PP::lr(p) >= LOG_E) return 1;
     return 2;
