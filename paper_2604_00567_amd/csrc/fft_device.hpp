@@ -514,9 +514,10 @@ struct PassPlan {
 // Exchanges in two rounds: a whole-transform unit (one per workgroup) whose
 // exchange would not fit in LDS writes and reads half of the exchange's rows
 // per round (binary16 2^16 points: 256 KiB of data, 128-135 KiB per round).
-// A binary16 2^15-point unit held as 64 elements on each of 512 lanes also
-// exchanges in two rounds although one would fit: 70 KiB of LDS instead of
-// 135, so two such workgroups share a CU.  Each pass after an exchange must
+// A unit of 128 KiB of data held as 64 elements per lane (binary16 2^15
+// points on 512 lanes, binary32 2^14 on 256) also exchanges in two rounds
+// although one would fit: about 70 KiB of LDS instead of 135, so two such
+// workgroups share a CU.  Each pass after an exchange must
 // hold at least two groups per lane (the rounds split a lane's groups in
 // halves).
 constexpr size_t kLdsBytes = 160 * 1024;
@@ -525,7 +526,7 @@ constexpr int exchange_rounds() {
     if (!(MODE == MODE_SMALL && UPW == 1 && PP::NP > 1))
         return 1;
     const bool over = (size_t)PP::region() * sizeof(E) > kLdsBytes;
-    const bool shared = sizeof(E) == 4 && LOG_E == 6 && PP::log_nu == 15;
+    const bool shared = LOG_E == 6 && (sizeof(E) << PP::log_nu) == ((size_t)128 << 10);
     if (!over && !shared) return 1;
     for (int p = 1; p < PP::NP; ++p)
         if (PP::lr(p) >= LOG_E) return 1;

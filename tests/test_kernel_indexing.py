@@ -77,13 +77,13 @@ LDS_BYTES = 160 * 1024
 
 def exchange_rounds(pp, mode, upw, log_e, esize):
     """Two rounds (half of the exchange's rows each) for a lone whole-transform
-    unit whose exchange does not fit, or a binary16 2^15-point unit of 64
+    unit whose exchange does not fit, or a unit of 128 KiB of data held as 64
     elements per lane (two of its workgroups then share a CU), when each later
     pass has two or more groups per lane."""
     if not (mode == 0 and upw == 1 and pp.np > 1):
         return 1
     over = pp.region() * esize > LDS_BYTES
-    shared = esize == 4 and log_e == 6 and pp.log_nu == 15
+    shared = log_e == 6 and (esize << pp.log_nu) == 128 << 10
     if not (over or shared):
         return 1
     if any(pp.lr(p) >= log_e for p in range(1, pp.np)):
