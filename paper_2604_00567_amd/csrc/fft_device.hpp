@@ -511,26 +511,30 @@ struct PassPlan {
     }
 };
 
-// Exchanges in two rounds: a whole-transform unit (one per workgroup) whose
-// exchange would not fit in LDS writes and reads half of the exchange's rows
-// per round (binary16 2^16 points: 256 KiB of data, 128-135 KiB per round).
-// A unit of 128 KiB of data held as 64 elements per lane (binary16 2^15
-// points on 512 lanes, binary32 2^14 on 256) also exchanges in two rounds
-// although one would fit: about 70 KiB of LDS instead of 135, so two such
-// workgroups share a CU.  Each pass after an exchange must
-// hold at least two groups per lane (the rounds split a lane's groups in
+// Exchanges in two rounds: a whole-transform unit (one per workgroup) writes
+// and reads half of the exchange's rows per round where its exchange would not
+// fit in LDS (binary16 2^16 points: 256 KiB of data, 128-135 KiB per round),
+// and also where halving the exchange lets more workgroups share a CU whose
+// one-round occupancy is below the 16 waves that lanes holding 256 bytes or
+// more of data leave registers for (binary16 2^15 points on 512 lanes: one
+// workgroup of 135 KiB or two of 70 KiB; binary32 2^14 on 256 lanes; binary32
+// 2^13 on 256 lanes: two workgroups or four).  Each pass after an exchange
+// must hold at least two groups per lane (the rounds split a lane's groups in
 // halves).
 constexpr size_t kLdsBytes = 160 * 1024;
 template <class E, int LOG_E, int MODE, int UPW, class PP>
 constexpr int exchange_rounds() {
     if (!(MODE == MODE_SMALL && UPW == 1 && PP::NP > 1))
         return 1;
-    const bool over = (size_t)PP::region() * sizeof(E) > kLdsBytes;
-    const bool shared = LOG_E == 6 && (sizeof(E) << PP::log_nu) == ((size_t)128 << 10);
-    if (!over && !shared) return 1;
     for (int p = 1; p < PP::NP; ++p)
         if (PP::lr(p) >= LOG_E) return 1;
-    return 2;
+    const size_t one = (size_t)PP::region() * sizeof(E), two = (size_t)PP::half_region() * sizeof(E);
+    if (one > kLdsBytes) return 2;
+    if ((sizeof(E) << LOG_E) < 256) return 1;
+    const int lanes = 1 << (PP::log_nu - LOG_E);
+    const int waves = lanes >= 64 ? lanes / 64 : 1;
+    const int wg1 = (int)(kLdsBytes / one), wg2 = (int)(kLdsBytes / two);
+    return (wg1 * waves < 16 && wg2 > wg1) ? 2 : 1;
 }
 // LDS elements of a workgroup.
 template <class E, int LOG_E, int MODE, int UPW, class PP>

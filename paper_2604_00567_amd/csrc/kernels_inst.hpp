@@ -43,6 +43,9 @@ static constexpr bool cfg_fits() {
         // the path-encoding variants: binary16 plans, plain (non-pipelined, no lane tail) kernels
         return false;
     }
+    // staged blocks pass through the whole exchange area, which a two-round
+    // exchange halves
+    if (STG && exchange_rounds<E, LOG_E, MODE, UPW, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>>() == 2) return false;
     return unit_fits<E, LOG_NU, LOG_E, MODE, UPW, LANE, PIPE, PassPlan<LOG_NU, LR0, LR1, LR2, LANE>, ENC>();
 }
 

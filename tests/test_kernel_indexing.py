@@ -77,18 +77,22 @@ LDS_BYTES = 160 * 1024
 
 def exchange_rounds(pp, mode, upw, log_e, esize):
     """Two rounds (half of the exchange's rows each) for a lone whole-transform
-    unit whose exchange does not fit, or a unit of 128 KiB of data held as 64
-    elements per lane (two of its workgroups then share a CU), when each later
-    pass has two or more groups per lane."""
+    unit whose exchange does not fit, or whose CU holds fewer than the 16
+    waves that lanes of 256 bytes or more leave registers for and would hold
+    more workgroups with the exchange halved, when each later pass has two or
+    more groups per lane."""
     if not (mode == 0 and upw == 1 and pp.np > 1):
-        return 1
-    over = pp.region() * esize > LDS_BYTES
-    shared = log_e == 6 and (esize << pp.log_nu) == 128 << 10
-    if not (over or shared):
         return 1
     if any(pp.lr(p) >= log_e for p in range(1, pp.np)):
         return 1
-    return 2
+    one, two = pp.region() * esize, pp.half_region() * esize
+    if one > LDS_BYTES:
+        return 2
+    if (esize << log_e) < 256:
+        return 1
+    waves = max(1, (1 << (pp.log_nu - log_e)) // 64)
+    wg1, wg2 = LDS_BYTES // one, LDS_BYTES // two
+    return 2 if (wg1 * waves < 16 and wg2 > wg1) else 1
 
 
 def lds_elems(pp, mode, upw, log_e, esize):
@@ -565,6 +569,8 @@ def compiled(c, dtype):
     if enc not in ("ENC_TABLE", "ENC_RADIX4") and (dtype != "f16" or pipe == 1 or lane):
         return False
     pp = PassPlan(log_nu, (lr0, lr1, lr2), lane)
+    if stg and exchange_rounds(pp, mode, upw, log_e, esize) == 2:
+        return False
     if pipe in (3, 4, 5) and lds_twiddle_entries(pp, log_nu, log_e, mode, lane, pipe) == 0 \
             and lds_row_twiddle_entries(c) == 0:
         return False
