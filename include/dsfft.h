@@ -392,8 +392,9 @@ void fft_serve_slot_destroy(fft_serve_slot* slot);
  *       one step per precision: the serving-slot kernels (fft_serve_slot_launch),
  *       or for a step of at most direct_max requests one cached-plan launch per
  *       request (two-pass plans on a workspace of the slot); with split_direct
- *       the step's split transforms take their cached two-pass plans in every
- *       step.  Steps on different slots overlap on the device.
+ *       the step's split transforms (those the slot kernels would split into
+ *       column and row items) take their cached plans in every step.  Steps on
+ *       different slots overlap on the device.
  *   FFT_SERVE_PER_REQUEST one cached plan (per shape and stream) and one launch
  *       per request, round-robin over `slots` streams, admitted in arrival
  *       order under the same budget (request data in a ring of
@@ -416,10 +417,11 @@ typedef struct {
     size_t budget_bytes;       /* HBM admission budget */
     size_t slot_bytes;         /* data bytes per slot and precision (continuous); ring size (per request) */
     uint64_t seed;             /* payload generator key */
-    int split_direct;          /* continuous: nonzero = split transforms always run through cached
-                                  two-pass plans on the slot's workspace, after the step's
-                                  whole-size requests, whose completion is observed on an event
-                                  of its own; zero = they run in the slot's kernels with the rest */
+    int split_direct;          /* continuous: nonzero = split transforms always run through their
+                                  cached plans (two-pass ones on the slot's workspace), after the
+                                  step's whole-size requests, whose completion is observed on an
+                                  event of its own; zero = they run in the slot's kernels with
+                                  the rest */
 } fft_serve_config;
 typedef struct {
     int64_t steps, direct_steps;
