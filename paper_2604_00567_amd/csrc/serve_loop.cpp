@@ -111,6 +111,8 @@ struct Trace {
 // Plans per (shape, key).  With a workspace for the key (one per stream in
 // the per-request loop), two-pass plans share it instead of owning their own:
 // launches on one stream are ordered, so they never use it at the same time.
+// The continuous loop keys every plan 0 and launches a two-pass plan on the
+// workspace of the slot that runs it.
 struct PlanCache {
     std::map<std::tuple<int64_t, int64_t, int, int>, fft_plan*> plans;
     int kind = 0;
@@ -380,6 +382,7 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
         }
         int64_t nxt = 0, head = 0, completed = 0;
         size_t inflight = 0;
+        size_t first_slot = 0;      // free slots are taken round-robin from here
         std::vector<int64_t> take;
         Group whole[2], split[2];
         double sum_req = 0;
@@ -427,7 +430,9 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
             // streams instead of one after another in one step
             int free_slots = 0;
             for (auto& x : slots) free_slots += x.busy ? 0 : 1;
-            for (size_t si = 0; si < slots.size(); ++si) {
+            const size_t first_free = first_slot;
+            for (size_t j = 0; j < slots.size(); ++j) {
+                const size_t si = (first_free + j) % slots.size();
                 Slot& s = slots[si];
                 if (s.busy || head >= nxt) continue;
                 size_t infl2 = inflight;
@@ -469,13 +474,21 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                         const int dt = d == 0 ? DT_F16 : DT_F32;
                         if (plans_only) {
                             for (size_t i = 0; i < g.rid.size() && rc == FFT_OK; ++i) {
-                                fft_plan* p = plans.get(g.n[i], g.b[i], dt, is_split(g.n[i], dt) ? (int)si : 0);
+                                // plans per shape; a two-pass plan runs on this
+                                // slot's workspace (launches on the slot's stream
+                                // are ordered, other slots have their own)
+                                fft_plan* p = plans.get(g.n[i], g.b[i], dt, 0);
                                 if (!p) {
                                     rc = FFT_ENOMEM;
                                     break;
                                 }
                                 char* ptr = (char*)s.arena[d] + (size_t)g.off[i] * ebytes(dt);
-                                rc = plan_execute(p, ptr, ptr, s.st);
+                                if (p->k2) {
+                                    rc = check_execute_args(p, ptr, ptr);
+                                    if (rc == FFT_OK) rc = launch_plan_ws(p, ptr, ptr, s.st, plans.ws[si], p->chunk);
+                                } else {
+                                    rc = plan_execute(p, ptr, ptr, s.st);
+                                }
                             }
                         } else {
                             rc = fft_serve_slot_launch(s.native[d], g.n.data(), g.b.data(), g.off.data(),
@@ -513,6 +526,7 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                 }
                 s.busy = true;
                 s.early_busy = two;
+                first_slot = (si + 1) % slots.size();
                 st.steps += 1;
                 st.direct_steps += direct ? 1 : 0;
                 sum_req += (double)take.size();
