@@ -464,9 +464,9 @@ int fft_serve_run(const fft_serve_config* cfg, const double* t, const int64_t* n
                                                     s.st)) != hipSuccess)
                         rc = hip_error(e, "launch(fill)");
                 }
-                // one group's transforms: cached plans (split sizes: a plan per
-                // slot, on the slot's workspace) or the slot's kernels; then the
-                // optional output copies
+                // one group's transforms: cached plans (two-pass ones on the
+                // slot's workspace) or the slot's kernels; then the optional
+                // output copies
                 auto run_group = [&](Group* gs, bool plans_only) {
                     for (int d = 0; d < 2 && rc == FFT_OK; ++d) {
                         const Group& g = gs[d];
