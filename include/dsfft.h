@@ -388,7 +388,8 @@ void fft_serve_slot_destroy(fft_serve_slot* slot);
  *       in and out, plus workspace for split transforms, on top of the bytes in
  *       flight) and the slot's capacities (slot_bytes of data per precision,
  *       max_transforms whole transforms, max_large split ones, max_items work
- *       items, max_step_requests requests), generates the step's data and runs
+ *       items of the slot's kernels as their work list would hold them,
+ *       max_step_requests requests), generates the step's data and runs
  *       one step per precision: the serving-slot kernels (fft_serve_slot_launch),
  *       or for a step of at most direct_max requests one cached-plan launch per
  *       request (two-pass plans on a workspace of the slot); with split_direct
@@ -445,7 +446,9 @@ int fft_serve_fill(fft_dtype dtype, void* data, int64_t elems, uint64_t first, u
  * position `head` of a trace whose requests have all arrived, with
  * inflight_bytes already in flight (the rule of FFT_SERVE_CONTINUOUS above).
  * taken receives up to cfg->max_step_requests request indices, *ntaken their
- * number, *inflight_out the bytes in flight after them. */
+ * number, *inflight_out the bytes in flight after them.  Returns FFT_EINVAL
+ * for a null argument, a negative head or count, a size that is not a power
+ * of two in [2, 2^18], a batch below 1 or a dtype other than FFT_F16/FFT_F32. */
 int fft_serve_admit(const int64_t* n, const int64_t* batch, const int32_t* dtype, int64_t count,
                     int64_t head, size_t inflight_bytes, const fft_serve_config* cfg, int64_t* taken,
                     int64_t* ntaken, size_t* inflight_out);

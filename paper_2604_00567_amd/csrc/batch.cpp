@@ -99,6 +99,18 @@ static Split split_for(int m) {
     }
 }
 
+int64_t work_items_of_class(int dtype, int m, int64_t count) {
+    if (count <= 0) return 0;
+    if (m <= kMaxSingleLog) {
+        const int64_t upw = cfg_upw(kSmallCfg[m]);
+        return (count + upw - 1) / upw;
+    }
+    if (m <= max_whole_log(dtype)) return 0;      // list kernels
+    const Split sp = split_for(m);
+    const int64_t cu = cfg_upw(sp.ccfg), ru = cfg_upw(sp.rcfg);
+    return count * (((int64_t(1) << sp.lm_c) + cu - 1) / cu + ((int64_t(1) << sp.lm_r) + ru - 1) / ru);
+}
+
 // Work items for transforms of sizes n[t] at element offsets off[t]:
 // phase 0 = the column items of every large transform (in input order), then
 // the single-unit items from the largest size down (so the end of the phase

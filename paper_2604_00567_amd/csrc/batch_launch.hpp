@@ -57,6 +57,11 @@ int cfg_upw(int cfg);                  // units per workgroup of a configuration
 void build_work(const int64_t* n, const int64_t* off, int64_t count, const int* cfg_choice,
                 int nlists, std::vector<HostBatchItem>& items, std::vector<int64_t>& offs,
                 std::vector<int64_t>& lists, int64_t* nlist, int64_t& ws_elems, int64_t& phase0);
+// Work items that `count` transforms of 2^m points add to a work list built
+// with kSmallCfg: whole transforms of one size share items of cfg_upw units,
+// list-kernel sizes take none, and each split transform takes its column and
+// row items.
+int64_t work_items_of_class(int dtype, int m, int64_t count);
 int batch_resident_grid(int dtype, int device, int* out);
 
 size_t batch_lds_bytes(int dtype);

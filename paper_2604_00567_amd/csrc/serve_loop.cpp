@@ -95,10 +95,18 @@ inline size_t ebytes(int dtype) { return dtype == DT_F16 ? 4 : 8; }
 inline bool is_split(int64_t n, int dtype) { return n > (int64_t(1) << max_whole_log(dtype)); }
 
 // What a step holds so far, per precision: elements, whole transforms, split
-// transforms and their elements (the slot's capacity checks).
+// transforms and their elements, transforms per size and the work items they
+// make (the slot's capacity checks).
 struct StepLoad {
     int64_t used[2] = {0, 0}, whole[2] = {0, 0}, large[2] = {0, 0}, large_elems[2] = {0, 0};
+    int64_t per_size[2][19] = {}, items[2] = {0, 0};
 };
+
+inline int log2_of(int64_t n) {
+    int m = 0;
+    while ((int64_t(1) << m) < n) ++m;
+    return m;
+}
 
 struct Trace {
     const double* t;
@@ -179,6 +187,14 @@ int64_t serve_admit(const Trace& tr, const int64_t* order, int64_t avail, int64_
         const int64_t elems = n * b;
         const int64_t cap = (int64_t)(c.slot_bytes / eb);
         if (ld.used[d] + elems > cap) break;
+        // work items of the slot's kernels (split transforms take none when
+        // they run through their plans)
+        const int m = log2_of(n);
+        const int64_t cnt = ld.per_size[d][m];
+        const int64_t more = c.split_direct && is_split(n, dt)
+                                 ? 0
+                                 : work_items_of_class(dt, m, cnt + b) - work_items_of_class(dt, m, cnt);
+        if (ld.items[d] + more > c.max_items) break;
         if (is_split(n, dt)) {
             if (ld.large[d] + b > c.max_large || (size_t)(ld.large_elems[d] + elems) * eb > c.slot_bytes) break;
             ld.large[d] += b;
@@ -187,6 +203,8 @@ int64_t serve_admit(const Trace& tr, const int64_t* order, int64_t avail, int64_
             if (ld.whole[d] + b > c.max_transforms) break;
             ld.whole[d] += b;
         }
+        ld.per_size[d][m] += b;
+        ld.items[d] += more;
         ld.used[d] += elems;
         take.push_back(r);
         inflight += nb;
@@ -286,6 +304,11 @@ int fft_serve_admit(const int64_t* n, const int64_t* batch, const int32_t* dtype
                     int64_t* ntaken, size_t* inflight_out) {
     if (!n || !batch || !dtype || !cfg || !taken || !ntaken || !inflight_out || head < 0 || count < 0)
         return set_error(FFT_EINVAL, "null argument");
+    for (int64_t r = 0; r < count; ++r) {
+        if (n[r] < 2 || (n[r] & (n[r] - 1)) || n[r] > (int64_t(1) << 18) || batch[r] < 1)
+            return set_error(FFT_EINVAL, "request sizes must be powers of two in [2, 2^18], batch >= 1");
+        if (dtype[r] != DT_F16 && dtype[r] != DT_F32) return set_error(FFT_EINVAL, "request dtype must be FFT_F16 or FFT_F32");
+    }
     std::vector<int64_t> order(count), take;
     for (int64_t i = 0; i < count; ++i) order[i] = i;
     Trace tr{nullptr, n, batch, dtype, count};

@@ -106,3 +106,48 @@ def test_split_rule_matches_the_library():
 def test_generator_offsets():
     tr = {"n": np.array([4, 8, 16, 2]), "batch": np.array([1, 2, 1, 3]), "dtype": np.array(["f16", "f32", "f16", "f32"])}
     assert generator_offsets(tr).tolist() == [0, 0, 4, 16]
+
+
+def _items(sizes, dt):
+    """Work items of the slot kernels for these transforms (the library's own list)."""
+    return binding.fft_batch_work_list(sizes, dt)[0].shape[0]
+
+
+def test_admission_work_item_capacity_whole_sizes():
+    # 256-point transforms share items of several units each: a step stops
+    # exactly where one more transform would open an item beyond max_items
+    k = 200
+    tr = {"n": np.full(k, 256, np.int64), "batch": np.ones(k, np.int64), "dtype": np.array(["f16"] * k)}
+    cfg = _cfg(1 << 40, max_step=k)
+    cfg.max_items = 1
+    take, _ = binding.fft_serve_admit(tr, 0, 0, cfg)
+    assert 1 < len(take) < k
+    assert _items([256] * len(take), "f16") == 1
+    assert _items([256] * (len(take) + 1), "f16") == 2
+
+
+def test_admission_work_item_capacity_split_sizes():
+    # binary32 2^15 transforms take the column/row split: each adds its column
+    # and row items, unless split transforms run through their plans
+    k = 40
+    n = 1 << 15
+    tr = {"n": np.full(k, n, np.int64), "batch": np.full(k, 4, np.int64), "dtype": np.array(["f32"] * k)}
+    per = _items([n], "f32")
+    assert per > 1
+    cfg = _cfg(1 << 40, slot_bytes=1 << 30, max_step=k)
+    cfg.max_items = 10 * per
+    take, _ = binding.fft_serve_admit(tr, 0, 0, cfg)
+    assert len(take) == 2                                 # 8 transforms; a third request makes 12
+    assert _items([n] * 8, "f32") <= cfg.max_items < _items([n] * 12, "f32")
+    cfg.split_direct = 1
+    take, _ = binding.fft_serve_admit(tr, 0, 0, cfg)
+    assert len(take) > 2
+
+
+def test_admission_rejects_bad_requests():
+    import pytest
+    cfg = _cfg(1 << 40)
+    for n, b, dt in ((1 << 19, 1, "f16"), (3, 1, "f16"), (256, 0, "f32")):
+        tr = {"n": np.array([n]), "batch": np.array([b]), "dtype": np.array([dt])}
+        with pytest.raises(RuntimeError):
+            binding.fft_serve_admit(tr, 0, 0, cfg)
