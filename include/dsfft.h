@@ -226,7 +226,9 @@ fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft
 fft_plan* fft_plan_create_radix4(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind,
                                  int direction, int variant);
 
-/* Number of compiled radix-4 configurations for (n, dtype). */
+/* Number of compiled radix-4 configurations for (n, dtype) (0 for
+ * FFT_F16_F32).  FFT_EINVAL for n not a power of two in [2, 2^20], a null
+ * count or an unknown dtype. */
 int fft_config_count_radix4(int64_t n, fft_dtype dtype, int* count);
 
 /*
@@ -259,7 +261,9 @@ int fft_tune(int64_t n, int64_t batch, fft_dtype dtype, fft_table_kind kind, int
 int fft_tuned_choice(int64_t n, fft_dtype dtype, int* variant_a, int* variant_b, int* two_pass);
 
 /* Number of compiled configurations for (n, dtype): *single for the
- * one-kernel schedule, *cols and *rows for the two kernels of the two-pass one. */
+ * one-kernel schedule, *cols and *rows for the two kernels of the two-pass one
+ * (each output may be NULL).  FFT_EINVAL for n not a power of two in
+ * [2, 2^20] or an unknown dtype. */
 int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows);
 
 /*

@@ -134,7 +134,9 @@ std::string describe(const KernelCfg* k) {
 
 // Largest single-kernel size per dtype: the largest whole-transform
 // configuration that fits (binary16 2^16 points, whose exchanges run in two
-// rounds through LDS; binary32 2^14); beyond it, the two-pass split.
+// rounds through LDS; binary32 and binary16 storage with binary32 butterflies
+// 2^15); beyond it, the two-pass split.  A tuning record may still choose the
+// split for a size that has a whole-transform configuration.
 static int small_limit(int dtype) {
     int m = 20;
     while (m > 0 && count_kernels(dtype, MODE_SMALL, m) == 0) --m;
@@ -445,6 +447,8 @@ int fft_config_count_radix4(int64_t n, fft_dtype dtype, int* count) {
     if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
         return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
     if (!count) return set_error(FFT_EINVAL, "null argument");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32 && (int)dtype != DT_F16F32)
+        return set_error(FFT_EINVAL, "bad dtype");
     int m = 0;
     while ((int64_t(1) << m) < n) ++m;
     *count = (int)dtype == DT_F16F32 ? 0 : count_kernels((int)dtype, MODE_SMALL, m, true);
@@ -478,6 +482,8 @@ fft_plan* fft_plan_create_variant(int64_t n, int64_t batch, fft_dtype dtype, fft
 int fft_config_count(int64_t n, fft_dtype dtype, int* single, int* cols, int* rows) {
     if (n < 2 || (n & (n - 1)) || n > (int64_t(1) << 20))
         return set_error(FFT_EINVAL, "n must be a power of two in [2, 2^20]");
+    if ((int)dtype != DT_F16 && (int)dtype != DT_F32 && (int)dtype != DT_F16F32)
+        return set_error(FFT_EINVAL, "bad dtype");
     int m = 0;
     while ((int64_t(1) << m) < n) ++m;
     const int m1 = (m + 1) / 2, m2 = m - m1;

@@ -79,6 +79,12 @@ def test_argument_validation_without_gpu():
         binding.fft_table_build(1024, 7, "dual_select")
     with pytest.raises(binding.FFTError):
         binding.fft_table_build(1024, "f16", 9)
+    for bad in (3, -1, 7):
+        with pytest.raises(binding.FFTError):
+            binding.fft_config_count(1024, bad)
+        with pytest.raises(binding.FFTError):
+            binding.fft_config_count_radix4(1024, bad)
+    assert binding.fft_config_count_radix4(1024, "f16f32") == 0
     binding.fft_destroy(None)   # NULL-safe
 
 
