@@ -4,7 +4,8 @@
 // same butterflies, so any difference is a defect), and records the fastest
 // in a process-wide registry that plan creation consults.  Records persist in
 // a plain-text file named by DSFFT_TUNE_FILE (one record per line:
-// "arch cus dtype log2n variant_a variant_b two_pass GB/s").  Records shipped
+// "arch cus dtype log2n variant_a variant_b two_pass GB/s"; '#' starts a
+// comment line).  Records shipped
 // with the library (tuning_records.txt beside libdsfft.so, measured on the
 // target device) are read first; DSFFT_TUNE_FILE records override them.
 #include <dlfcn.h>
@@ -47,13 +48,28 @@ static std::string device_tag() {
     return arch + " " + std::to_string(prop.multiProcessorCount);
 }
 
+// One record per line; blank lines, lines starting with '#' and lines that do
+// not hold a well-formed record are skipped, so one bad line costs only itself.
 static void read_records(const std::string& path, const std::string& tag) {
     FILE* f = std::fopen(path.c_str(), "r");
     if (!f) return;
-    char arch[64];
-    int cus, dt, m, va, vb, two;
-    double gbs;
-    while (std::fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &cus, &dt, &m, &va, &vb, &two, &gbs) == 8) {
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        const size_t len = std::strlen(line);
+        if (len + 1 == sizeof line && line[len - 1] != '\n') {      // overlong: skip the rest
+            int c;
+            while ((c = std::fgetc(f)) != EOF && c != '\n') {
+            }
+            continue;
+        }
+        const char* q = line + std::strspn(line, " \t");
+        if (*q == '#' || *q == '\n' || *q == '\0') continue;
+        char arch[64];
+        int cus, dt, m, va, vb, two;
+        double gbs;
+        if (std::sscanf(q, "%63s %d %d %d %d %d %d %lf", arch, &cus, &dt, &m, &va, &vb, &two, &gbs) != 8) continue;
+        if (dt < DT_F16 || dt > DT_F16F32 || m < 1 || m > 20 || va < 0 || vb < 0 || (two != 0 && two != 1))
+            continue;
         if (tag != std::string(arch) + " " + std::to_string(cus)) continue;
         g_tuned[std::make_tuple(dt, m)] = TuneRec{va, vb, two, gbs};
     }
