@@ -248,7 +248,8 @@ int fft_table_build_radix4(int64_t n, fft_dtype dtype, fft_table_kind kind, int 
  * lane (waves per transform), LDS staging, cross-lane tail, single-kernel or
  * two-pass -- on `batch` synthetic transforms with HIP events (`reps` timed
  * executions each), accepts a candidate only if its output is bit-identical
- * to the default configuration's, and records the fastest: later
+ * to the first configuration that runs (the default one, unless it fails),
+ * and records the fastest: later
  * fft_plan_create calls for this (n, dtype) in the process use it, and the
  * record is appended to the file named by the DSFFT_TUNE_FILE environment
  * variable (read back at the first plan creation of a process).  `report`
