@@ -1,6 +1,7 @@
 """Generates tuning records for this device: runs the library's autotuner
 (fft_tune: every compiled configuration timed with HIP events, only outputs
-bit-identical to the default configuration accepted) for N = 2^1 .. 2^20 in
+bit-identical to the first configuration that runs, normally the default,
+accepted) for N = 2^1 .. 2^20 in
 each precision and appends the winners to --out (the DSFFT_TUNE_FILE
 format).  Copy the file beside libdsfft.so as tuning_records.txt to make the
 records the library's defaults.
