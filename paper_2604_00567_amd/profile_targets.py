@@ -3,7 +3,7 @@
 
     python -m paper_2604_00567_amd.profile_targets large      # N = 2^15..2^20
     python -m paper_2604_00567_amd.profile_targets batch      # uneven batch
-    python -m paper_2604_00567_amd.profile_targets fixed N BATCH DTYPE
+    python -m paper_2604_00567_amd.profile_targets fixed N BATCH DTYPE   # f16, f32, f16f32
 
 Every run starts with three plain 256 MiB device-to-device copies, the
 calibration for counter passes (what FETCH_SIZE / WRITE_SIZE read for a copy
@@ -17,7 +17,7 @@ import torch
 
 from . import binding, inputs
 
-TORCH_DTYPE = {"f16": torch.float16, "f32": torch.float32}
+TORCH_DTYPE = {"f16": torch.float16, "f32": torch.float32, "f16f32": torch.float16}
 
 
 def run_fixed(n: int, batch: int, dtype: str, reps: int = 6) -> None:
