@@ -21,6 +21,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace dsfft {
 
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
@@ -92,6 +94,25 @@ __device__ __forceinline__ void bfly(f2_t& a, f2_t& b, const TwF tw) {
     B.y = __builtin_fmaf(-s2, tw.m, a.y);
     a = A;
     b = B;
+}
+
+// The same binary32 butterfly on operands still held as stored binary16 pairs
+// (the first stage of a binary16-storage plan): the path's operand order is a
+// rotate of the packed pair by 16 bits, and each widening, which is exact,
+// folds into its FMA (v_fma_mix_f32), so the FMAs, their operands and their
+// roundings are those of widening first and calling bfly.
+__device__ __forceinline__ void bfly_stored(uint32_t a, uint32_t b, const TwF tw, f2_t& A, f2_t& B) {
+    const uint32_t c = __builtin_amdgcn_alignbit(b, b, tw.mask & 16u);
+    const float cr = (float)__builtin_bit_cast(_Float16, (uint16_t)c);
+    const float ci = (float)__builtin_bit_cast(_Float16, (uint16_t)(c >> 16));
+    const float ar = (float)__builtin_bit_cast(_Float16, (uint16_t)a);
+    const float ai = (float)__builtin_bit_cast(_Float16, (uint16_t)(a >> 16));
+    const float s1 = __builtin_fmaf(-tw.t, ci, cr);
+    const float s2 = __builtin_fmaf(tw.t, cr, ci);
+    A.x = __builtin_fmaf(s1, tw.sm, ar);
+    A.y = __builtin_fmaf(s2, tw.m, ai);
+    B.x = __builtin_fmaf(-s1, tw.sm, ar);
+    B.y = __builtin_fmaf(-s2, tw.m, ai);
 }
 
 // Encodings of the path choice (the select flag of Sec. III; Sec. VI notes
@@ -446,14 +467,16 @@ __device__ __forceinline__ void reg_pass4(E* v, const TW* tw) {
     }
 }
 
-template <int LR, int ENC = ENC_TABLE, bool ODD = false, class E, class TW>
+// T0 > 1: stages before T0 are done already (a binary16-storage first pass).
+template <int LR, int ENC = ENC_TABLE, bool ODD = false, int T0 = 1, class E, class TW>
 __device__ __forceinline__ void reg_pass(E* v, const TW* tw) {
     if constexpr (ENC == ENC_RADIX4) {
+        static_assert(T0 == 1, "radix-4 passes start at their first stage");
         reg_pass4<LR, ODD>(v, tw);
     } else {
         constexpr int R = 1 << LR;
 #pragma unroll
-        for (int t = 1; t <= LR; ++t) {
+        for (int t = T0; t <= LR; ++t) {
             const int H = R >> t;
             E nv[R];
 #pragma unroll
@@ -784,7 +807,10 @@ using GridGeo = GridGeoT<false>;
 
 // Pass-0 inputs of this lane straight from HBM (unstaged configurations):
 // group r = g + G u (residue r, span 1) takes elements r + M i, i < R.
-// The streaming hint is used only where a wave's accesses cover whole lines.
+// The streaming hint is used only where a wave's accesses cover whole lines:
+// per instruction the G lanes of a unit read G consecutive elements, so where
+// those fill a 128-byte line (elsewhere the line's other elements come with
+// the lane's later loads and must still be cached then).
 template <class E, int LOG_NU, int LOG_E, int UPW, int UPL, int MODE, int LR0, int LR1, int LR2, int LANE,
           class Geo, class SI>
 __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
@@ -830,7 +856,7 @@ __device__ __forceinline__ void load_pass0(E* v, const SI* in, const Geo& gp) {
 #pragma unroll
                 for (int i = 0; i < R; ++i) {
                     const int64_t idx = r + (int64_t)M * i;
-                    vk[u * R + i] = load_elem<MODE != MODE_COLS, E>(in + geo.base_in + idx * geo.in_stride);
+                    vk[u * R + i] = load_elem<MODE != MODE_COLS && G * (int)sizeof(SI) >= 128, E>(in + geo.base_in + idx * geo.in_stride);
                 }
             }
         } else {
@@ -989,6 +1015,13 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
             asm volatile("" ::: "memory");
         }
 
+        // binary16-storage plans (binary32 butterflies): pass 0 keeps the stored
+        // pairs for its first stage (bfly_stored), which widens them inside
+        // its FMAs
+        constexpr bool STORED0 = P == 0 && !PRE && !STG && std::is_same_v<E, f2_t> &&
+                                 std::is_same_v<SI, uint32_t> && Geo::kEncoding == ENC_TABLE;
+        uint32_t raw[STORED0 ? (UPL << LOG_E) : 1];
+
         // ---- gather
         if constexpr (P == 0 && STG) {
             // The workgroup's units are contiguous in memory (whole transforms,
@@ -1007,6 +1040,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
                     for (int i = 0; i < R; ++i) v[k * EL + u * R + i] = nat[r + M * i];
                 }
             }
+        } else if constexpr (STORED0) {
+            load_pass0<uint32_t, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(raw, in, gp);
         } else if constexpr (P == 0) {
             if constexpr (!PRE) load_pass0<E, LOG_NU, LOG_E, UPW, UPL, MODE, LR0, LR1, LR2, LANE>(v, in, gp);
         } else if constexpr (XR == 2) {
@@ -1060,8 +1095,20 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
             }
             // radix-4 form: the first pass of an odd log2 N starts with the span-2 stage
             constexpr bool ODD = Geo::kEncoding == ENC_RADIX4 && P == 0 && (LOG_NU & 1);
+            if constexpr (STORED0) {
+                // stage 1 of the pass pairs element i with i + R/2 under entry 1
 #pragma unroll
-            for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding, ODD>(v + k * EL + u * R, tw);
+                for (int k = 0; k < UPL; ++k) {
+                    E* vg = v + k * EL + u * R;
+                    const uint32_t* rg = raw + k * EL + u * R;
+#pragma unroll
+                    for (int i = 0; i < R / 2; ++i) bfly_stored(rg[i], rg[i + R / 2], tw[1], vg[i], vg[i + R / 2]);
+                    reg_pass<LR, Geo::kEncoding, ODD, 2>(vg, tw);
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < UPL; ++k) reg_pass<LR, Geo::kEncoding, ODD>(v + k * EL + u * R, tw);
+            }
         }
         if constexpr (PFN) {
             // entries c >= 1 of each group are the loaded ones
@@ -1202,7 +1249,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
 #pragma unroll
                         for (int e = 0; e < R; ++e) {
                             const int64_t idx = q + (int64_t)L0 * e;
-                            store_elem<MODE == MODE_SMALL>(v[k * EL + u * R + e],
+                            // streaming only where the G lanes' elements fill whole lines (as load_pass0)
+                            store_elem<MODE == MODE_SMALL && G * (int)sizeof(SO) >= 128>(v[k * EL + u * R + e],
                                                            out + geo.base_out + idx * geo.out_stride);
                         }
                     }
