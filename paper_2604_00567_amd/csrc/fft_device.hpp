@@ -1249,8 +1249,11 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
 #pragma unroll
                         for (int e = 0; e < R; ++e) {
                             const int64_t idx = q + (int64_t)L0 * e;
-                            // streaming only where the G lanes' elements fill whole lines (as load_pass0)
-                            store_elem<MODE == MODE_SMALL && G * (int)sizeof(SO) >= 128>(v[k * EL + u * R + e],
+                            // streaming only where one instruction's elements fill whole lines:
+                            // G consecutive ones of a whole transform (as load_pass0), or the
+                            // row kernel's UPW consecutive rows
+                            store_elem<(MODE == MODE_SMALL && G * (int)sizeof(SO) >= 128) ||
+                                       (MODE == MODE_ROWS && UPW * (int)sizeof(SO) >= 128)>(v[k * EL + u * R + e],
                                                            out + geo.base_out + idx * geo.out_stride);
                         }
                     }
