@@ -74,8 +74,8 @@ def test_every_table_kind_n1024(dtype, kind):
 
 
 @pytest.mark.parametrize("dtype", ["f16", "f32"])
-@pytest.mark.parametrize("n", [128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 15, 1 << 16, 1 << 18,
-                               1 << 20])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384, 1 << 15, 1 << 16,
+                               1 << 18, 1 << 20])
 def test_every_compiled_configuration(dtype, n):
     """Every single-kernel configuration, and every column x row pair of the
     two-pass schedule, bit for bit against the oracle."""
