@@ -979,8 +979,8 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
         constexpr bool unit_fast = (MODE == MODE_COLS) || (MODE == MODE_ROWS && P == NP - 1);
         static_assert(UPL == 1 || (MODE == MODE_SMALL && !LANE && UPW % UPL == 0),
                       "several units per lane: whole-transform units without the lane tail");
-        static_assert(!STG || (sizeof(SI) == sizeof(E) && sizeof(SO) == sizeof(E)),
-                      "16-byte staging copies stored values unchanged");
+        static_assert(!STG || !LANE || (sizeof(SI) == sizeof(E) && sizeof(SO) == sizeof(E)),
+                      "the lane tail's staging copies stored values unchanged");
         constexpr int XR = exchange_rounds<E, LOG_E, MODE, UPW, PP>();
         static_assert(XR == 1 || (UPL == 1 && !LANE && !STG && PRE == 0),
                       "two-round exchanges: one plain unit per workgroup");
@@ -1028,16 +1028,19 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
             // or consecutive rows of the workspace): copy the block into LDS
             // (natural order) with 16-byte streaming loads, then gather the
             // pass's decimated groups from LDS.
-            stage_in<E, NT_OF, UPW << LOG_NU>(in, lds, gp.block_first(LOG_NU),
-                                              gp.block_units(UPW) << LOG_NU);
+            // (stored values: widened as they are gathered where storage and
+            // compute precision differ)
+            SI* lds_in = reinterpret_cast<SI*>(lds);
+            stage_in<SI, NT_OF, UPW << LOG_NU>(in, lds_in, gp.block_first(LOG_NU),
+                                               gp.block_units(UPW) << LOG_NU);
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
-                const E* nat = lds + (ul0 + k) * NU;
+                const SI* nat = lds_in + (ul0 + k) * NU;
 #pragma unroll
                 for (int u = 0; u < GPL; ++u) {
                     const int r = g + G * u;
 #pragma unroll
-                    for (int i = 0; i < R; ++i) v[k * EL + u * R + i] = nat[r + M * i];
+                    for (int i = 0; i < R; ++i) v[k * EL + u * R + i] = to_compute(nat[r + M * i], E{});
                 }
             }
         } else if constexpr (STORED0) {
@@ -1208,20 +1211,22 @@ __device__ __forceinline__ void unit_pass(E* v, E* lds, const TwT<E, Geo::kEncod
         } else if constexpr (STG && MODE == MODE_SMALL) {
             // outputs to LDS in natural order, then 16-byte streaming stores
             // (row units stage only their input: their outputs are strided)
+            // (rounded to the storage precision as they are written)
             __syncthreads();                      // every lane is done reading LDS
+            SO* lds_out = reinterpret_cast<SO*>(lds);
 #pragma unroll
             for (int k = 0; k < UPL; ++k) {
-                E* nat = lds + (ul0 + k) * NU;
+                SO* nat = lds_out + (ul0 + k) * NU;
 #pragma unroll
                 for (int u = 0; u < GPL; ++u) {
                     const int q = g + G * u;
 #pragma unroll
-                    for (int e = 0; e < R; ++e) nat[q + L0 * e] = v[k * EL + u * R + e];
+                    for (int e = 0; e < R; ++e) nat[q + L0 * e] = to_storage(v[k * EL + u * R + e], SO{});
                 }
             }
             __syncthreads();
-            stage_out<E, NT_OF, UPW << LOG_NU>(lds, out, gp.block_first(LOG_NU),
-                                               gp.block_units(UPW) << LOG_NU);
+            stage_out<SO, NT_OF, UPW << LOG_NU>(lds_out, out, gp.block_first(LOG_NU),
+                                                gp.block_units(UPW) << LOG_NU);
         } else if constexpr (MODE == MODE_SMALL && Geo::kBlockRsrc && NU * sizeof(SO) > 4096) {
             const rsrc_t rs = block_rsrc(out + gp.block_first(LOG_NU), gp.block_units(UPW) << LOG_NU);
 #pragma unroll

@@ -24,14 +24,14 @@ struct IoOf {
 };
 
 // Whether a configuration is compiled for (E, S): it fits a workgroup's LDS,
-// with S != E it is neither staged (16-byte copies move stored values
-// unchanged) nor pipelined, and a path encoding other than the table's is a
+// with S != E it is not pipelined, nor staged with the lane tail (whose
+// 16-byte copies move stored values unchanged), and a path encoding other than the table's is a
 // binary16 variant of a plain kernel.
 template <class E, class S, int LOG_NU, int LOG_E, int UPW, int MODE, int LR0, int LR1, int LR2, int STG,
           int LANE, int PIPE, int ENC>
 static constexpr bool cfg_fits() {
     if constexpr (!std::is_same_v<E, S>)
-        if (STG || PIPE == 1) return false;
+        if ((STG && LANE) || PIPE == 1) return false;
     // the radix-4 form: whole transforms stored as computed, no lane tail, no
     // second register set or prefetch, passes on radix-4 stage boundaries
     if (ENC == ENC_RADIX4) {

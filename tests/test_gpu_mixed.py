@@ -23,7 +23,7 @@ def test_mixed_all_sizes(logn):
     assert mismatches(y, ref) == 0
 
 
-@pytest.mark.parametrize("n", [256, 1024, 4096, 16384, 1 << 15, 1 << 16, 1 << 20])
+@pytest.mark.parametrize("n", [8, 16, 32, 64, 128, 256, 1024, 4096, 16384, 1 << 15, 1 << 16, 1 << 20])
 def test_every_compiled_mixed_configuration(n):
     single, cols, rows = binding.fft_config_count(n, "f16f32")
     assert single + cols * rows > 0

@@ -564,7 +564,7 @@ def compiled(c, dtype):
         if lr0 % 2 != log_nu % 2 or lr1 % 2 or lr2 % 2:
             return False
         twsize *= 4
-    if dtype == "f16f32" and (stg or pipe == 1):
+    if dtype == "f16f32" and ((stg and lane) or pipe == 1):
         return False
     if enc not in ("ENC_TABLE", "ENC_RADIX4") and (dtype != "f16" or pipe == 1 or lane):
         return False
