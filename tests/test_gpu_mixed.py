@@ -71,3 +71,29 @@ def test_mixed_rejected_where_unsupported():
         binding.Batch([1024, 64], "f16f32")
     with pytest.raises(binding.FFTError):
         binding.fft_serve_slot_create("f16f32", "dual_select", 16, 16, 1, 1 << 20)
+
+
+@pytest.mark.parametrize("n", [16, 1024])
+def test_mixed_special_values(n):
+    """Infinities, NaNs, binary16 subnormals, the largest binary16 value and
+    -0 through the binary16-storage plans, whose first stage widens its
+    operands inside its FMAs (N = 1024) or after staging through LDS (N = 16),
+    bit for bit against the oracle (NaN matching NaN)."""
+    batch = 8
+    x = inputs.uniform(n, batch, 19, "f16")
+    flat = x.reshape(-1)
+    rng = np.random.default_rng(1)
+    idx = rng.choice(flat.size, min(64, flat.size), replace=False)
+    flat[idx[:6]] = np.inf
+    flat[idx[6:12]] = -np.inf
+    flat[idx[12:18]] = np.nan
+    flat[idx[18:40]] = np.float16(2.0 ** -24) * rng.integers(-1023, 1024, 22)   # subnormals
+    flat[idx[40:48]] = np.float16(65504.0)
+    flat[idx[48:]] = np.float16(-0.0)
+    x[0] = 0.0                                                                  # an all-zero transform
+    x[1] = np.float16(2.0 ** -24)                                               # all smallest subnormal
+    x[2] = np.float16(2.0 ** -24) * rng.integers(-1023, 1024, x[2].shape)      # subnormals only
+    y = run_gpu(x, "f16f32", "dual_select")
+    ref = oracle.emulate(x, "dual_select", "f16f32")
+    print(f"n={n} mismatches={mismatches(y, ref)}", flush=True)
+    assert mismatches(y, ref) == 0
